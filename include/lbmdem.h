@@ -1,0 +1,196 @@
+/*
+ * lbmdem: MI355X (gfx950) library for the four-way coupled lattice Boltzmann /
+ * discrete element method of Rettinger & Ruede, "An efficient four-way coupled
+ * lattice Boltzmann - discrete element method for fully resolved simulations of
+ * particle-laden flows" (arXiv:2003.01490).
+ *
+ * One time step is Algorithm 1 of the paper:
+ *   boundary conditions on particle and wall links, Eq. (MEM_CLI), with
+ *   bounce-back where CLI lacks a second fluid node (Sec. 2.2);
+ *   momentum-exchange force and torque per particle, Eqs. (MEM_Fq),
+ *   (interaction_force), (interaction_torque), plus 2 w_q c_q for missing links,
+ *   averaged over two time steps (Sec. 4.2);
+ *   D3Q19 stream + collide, Eqs. (LBM_Collide), (LBM_Stream), with the adaptive
+ *   TRT+aB operator of Sec. 2.3.2 (Eqs. MRT, TRTmatrix, TRTbulkmatrix);
+ *   n_sub DEM sub-cycles: velocity-Verlet (Eqs. velocity_verlet_1/2),
+ *   lubrication correction (Sec. 3.1), linear spring-dashpot contacts with
+ *   Coulomb friction (Sec. 4.1.2), gravity and buoyancy;
+ *   re-mapping of the spheres (Sec. 2.2) and PDF reconstruction in uncovered
+ *   cells, Eq. (PDF_reconstruction).
+ *
+ * Units and layout: lattice units (dx = dt = rho0 = 1).  Cell (i,j,k) has its
+ * centre at (i+1/2, j+1/2, k+1/2); arrays are x-fastest, index
+ * i + nx*(j + ny*k); PDF arrays are q-major (19 planes of N cells).  An axis
+ * with walls carries one wall-cell layer at each end; the wall planes lie at 1
+ * and n-1.  The D3Q19 velocity order is the one fixed by rows 2-4 of the
+ * moment matrix in App. A of the paper.
+ *
+ * Memory: every device buffer of a domain lives inside one region of
+ * lbmdem_footprint_bytes() bytes.  The caller passes it in (e.g. a PyTorch
+ * tensor) and keeps ownership: it must outlive the domain and is never freed
+ * by the library.  With dev_buf == NULL the library allocates and frees it.
+ * All device work of a domain is enqueued on the HIP stream given at creation.
+ *
+ * Errors: every function returns a status code (LBMDEM_OK or a negative
+ * LBMDEM_E* value); nothing throws or aborts across this interface.  After a
+ * failure, lbmdem_last_error() describes it.  A domain is not thread-safe;
+ * distinct domains are independent.
+ */
+#ifndef LBMDEM_H
+#define LBMDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBMDEM_OK = 0,
+  LBMDEM_EINVAL = -1,    /* invalid argument or configuration            */
+  LBMDEM_ENOMEM = -2,    /* region too small / allocation failed          */
+  LBMDEM_EDEVICE = -3,   /* HIP runtime error                              */
+  LBMDEM_EOVERLAP = -4,  /* sphere overlaps a wall or another sphere       */
+  LBMDEM_EUNSTABLE = -5, /* non-finite particle state detected             */
+  LBMDEM_ECAPACITY = -6, /* max_spheres / contact or neighbour slots full  */
+  LBMDEM_ESTATE = -7     /* domain already failed                          */
+};
+
+enum { LBMDEM_TRT_AB = 0, LBMDEM_TRT_B = 1, LBMDEM_TRT = 2, LBMDEM_SRT = 3 };
+enum { LBMDEM_BC_CLI = 0, LBMDEM_BC_BOUNCE_BACK = 1 };
+enum { LBMDEM_STORE_F64 = 0, LBMDEM_STORE_F32 = 1, LBMDEM_STORE_F16 = 2 };
+enum { LBMDEM_FREE = 0, LBMDEM_PRESCRIBED = 1, LBMDEM_FIXED = 2 };
+enum {
+  LBMDEM_FIELD_RHO = 0,   /* double[N]                                      */
+  LBMDEM_FIELD_VEL = 1,   /* double[3N], component-major                    */
+  LBMDEM_FIELD_PDF = 2,   /* double[19N], full f (not the stored deviation) */
+  LBMDEM_FIELD_FLAGS = 3, /* uint8[N]: 0 fluid, 1 fluid in TRT+aB shell,
+                             2 solid, 3 wall                                */
+  LBMDEM_FIELD_OWNER = 4  /* int32[N]: sphere id of solid cells, else -1   */
+};
+
+typedef struct lbmdem_config {
+  int32_t nx, ny, nz;
+  int32_t walls[3];         /* per axis: 0 periodic, 1 wall layers at both ends */
+  double wall_u_lo[3];      /* velocity of the wall at z = 1 (fluid side only)  */
+  double wall_u_hi[3];      /* velocity of the wall at z = nz-1                 */
+  double nu;                /* kinematic viscosity, Eq. (Viscosity)             */
+  double magic_lambda;      /* Eq. (MagicParameter); paper: 3/16                */
+  double lambda_b;          /* Eq. (lambda_b) in the shell; paper: 100          */
+  double delta_ab;          /* TRT+aB shell thickness; paper: 2                 */
+  int32_t collision;        /* LBMDEM_TRT_AB (default), _TRT_B, _TRT, _SRT      */
+  int32_t boundary;         /* LBMDEM_BC_CLI (default) or _BOUNCE_BACK          */
+  int32_t storage;          /* PDF storage: LBMDEM_STORE_F64/_F32/_F16; the two
+                               reduced forms store f - w_q and collide in FP32 */
+  int32_t n_sub;            /* DEM sub-cycles per time step; paper: 10          */
+  int32_t force_averaging;  /* 1: average F_fp, T_fp over two time steps        */
+  double gravity[3];
+  double e_dry;             /* dry restitution coefficient                       */
+  double poisson_ratio;     /* Eq. (tangentialCollisionParameters)               */
+  double friction;          /* Coulomb coefficient mu_p                          */
+  double tc;                /* > 0 collision time; <= 0: 2.31 D / c_s per contact */
+  double dmin;              /* >= 0 minimal lubrication gap; < 0: (0.001 + 0.00007 R) R */
+  double cut_n, cut_tt, cut_tr; /* lubrication cut-offs; paper: 2/3, 1/2, 1/2   */
+  int32_t lub_mask;         /* bit0 normal, bit1 tangential translation, bit2 rotation */
+  int32_t max_spheres;      /* capacity, sizes the device region                 */
+  double max_radius;        /* largest sphere radius that will be added          */
+} lbmdem_config;
+
+typedef struct lbmdem_domain lbmdem_domain;
+
+/* Fills *cfg with the paper's parameters (Lambda = 3/16, Lambda_b = 100,
+ * delta_aB = 2, cut-offs 2/3, 1/2, 1/2, n_sub = 10, T_c and delta_min by the
+ * paper's relations) on a 32^3 domain with z walls, FP32 storage. */
+int32_t lbmdem_config_init(lbmdem_config* cfg);
+
+/* Exact number of device bytes a domain with this configuration needs.
+ * Pure; makes no device call.  Returns 0 for an invalid configuration. */
+size_t lbmdem_footprint_bytes(const lbmdem_config* cfg);
+
+/* Creates a domain: fluid at rest (rho = 1, u = 0), no spheres.  dev_buf is a
+ * device region of at least lbmdem_footprint_bytes(cfg) bytes, 256-byte
+ * aligned, owned by the caller (NULL: the library allocates one).  hip_stream
+ * is a hipStream_t (NULL: the null stream).  *out receives the handle. */
+int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
+                      void* hip_stream, lbmdem_domain** out);
+
+/* Releases host resources and any library-owned device region.  Null-safe. */
+int32_t lbmdem_destroy(lbmdem_domain* dom);
+
+/* Adds n spheres (host arrays of 3n positions, velocities, angular
+ * velocities; n radii and densities), borrowed for the call.  ids_out (may be
+ * NULL) receives their ids, which are dense and stable.  Returns
+ * LBMDEM_EOVERLAP if a sphere crosses a wall plane or overlaps another sphere,
+ * LBMDEM_ECAPACITY beyond max_spheres, LBMDEM_EINVAL if R > max_radius.
+ * The particles are mapped at once. */
+int32_t lbmdem_add_spheres(lbmdem_domain* dom, int32_t n, const double* x,
+                           const double* u, const double* w, const double* radius,
+                           const double* rho, int32_t* ids_out);
+
+/* Overwrites positions (mask bit 0), velocities (bit 1), angular velocities
+ * (bit 2) of n spheres between steps and re-maps them (uncovered cells are
+ * reconstructed).  Host arrays, 3 doubles per sphere. */
+int32_t lbmdem_update_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids,
+                              const double* x, const double* u, const double* w,
+                              int32_t mask);
+
+/* Motion mode of a sphere: LBMDEM_FREE, LBMDEM_FIXED (state never changes),
+ * or LBMDEM_PRESCRIBED: velocity u_target (1 - exp(-c_acc t / t_st)) from rest
+ * (Eq. artificial_acceleration), released to free motion once the gap to a
+ * wall plane falls below release_gap. */
+int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode,
+                               const double* u_target, double c_acc, double t_st,
+                               double release_gap);
+
+/* Enqueues nsteps coupled time steps on the domain's stream; returns without
+ * waiting. */
+int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps);
+
+/* Waits for the domain's stream and reports device-side failures
+ * (LBMDEM_EUNSTABLE, LBMDEM_ECAPACITY). */
+int32_t lbmdem_sync(lbmdem_domain* dom);
+
+/* Number of spheres added so far. */
+int32_t lbmdem_num_spheres(const lbmdem_domain* dom);
+
+/* Synchronising copy of the state of sphere `id` into out[42] (host):
+ *  0 x  3 u  6 w  9 F_fp 12 T_fp (averaged resolved hydrodynamic force/torque)
+ * 15 F_tot 18 T_tot (total of the last sub-step) 21 F_lub 24 T_lub 27 F_col
+ * 30 T_col 33 mode 34 R 35 rho 36 F_raw 39 T_raw (resolved, not averaged). */
+int32_t lbmdem_get_sphere_state(lbmdem_domain* dom, int32_t id, double* out);
+
+/* Synchronising copy of a whole-lattice field (LBMDEM_FIELD_*) to dst (host,
+ * or device when dst_is_device != 0) of `bytes` bytes; non-fluid cells read 0
+ * in RHO, VEL and PDF. */
+int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t bytes,
+                         int32_t dst_is_device);
+
+/* Overwrites all PDFs with the full distributions f (host, double[19N],
+ * q-major), rounded to the storage precision, and recomputes the boundary
+ * values of the next step. */
+int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f);
+
+/* Kernel timing with HIP events on the domain's stream (for roofline
+ * reports).  kernel: 0 fused stream-collide sweep, 1 DEM, 2 mapping + boundary.
+ * get returns the summed milliseconds and launch count since enabling. */
+int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable);
+int32_t lbmdem_get_profile(lbmdem_domain* dom, int32_t kernel, double* total_ms,
+                           int64_t* count);
+
+/* Algorithmic HBM bytes one sweep launch must move (19 loads + 19 stores of
+ * the stored PDF type per cell plus the cell flag byte) for this domain. */
+double lbmdem_sweep_bytes(const lbmdem_domain* dom);
+
+/* Plain device-to-device copy kernel on `hip_stream` (bandwidth calibration
+ * for hardware counters). */
+int32_t lbmdem_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+/* Human-readable description of the last failure on this domain (or of the
+ * last failed create when dom is NULL); valid until the next call. */
+const char* lbmdem_last_error(const lbmdem_domain* dom);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

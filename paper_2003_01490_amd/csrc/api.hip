@@ -1,0 +1,671 @@
+// Host side of the lbmdem C-ABI: configuration checks, the layout of the
+// caller-owned device region, sphere management, step orchestration on the
+// domain's stream, read-out and profiling.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "lbmdem.h"
+
+using namespace lbmdem;
+
+namespace {
+
+constexpr double PI_H = 3.14159265358979323846;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t storage_size(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
+
+int zblocks(const lbmdem_config& c) {
+  const int e = 2 * (int)std::ceil(c.max_radius + c.delta_ab) + 6;
+  return std::max(1, std::min(c.nz, e));
+}
+
+struct Layout {
+  size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
+  size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
+      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, partial, status;
+  size_t total;
+};
+
+Layout make_layout(const lbmdem_config& c) {
+  Layout L;
+  const size_t N = (size_t)c.nx * c.ny * c.nz;
+  const size_t P = (size_t)std::max(c.max_spheres, 1);
+  const size_t sz = storage_size(c.storage);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.pdf0 = take((size_t)Q * N * sz);
+  L.pdf1 = take((size_t)Q * N * sz);
+  L.flags = take(N);
+  L.owner = take(4 * N);
+  L.claim = take(8 * N);
+  L.shellstamp = take(4 * N);
+  L.stage = take(8 * N);
+  L.x = take(24 * P);
+  L.u = take(24 * P);
+  L.w = take(24 * P);
+  L.xmap = take(24 * P);
+  L.R = take(8 * P);
+  L.rho = take(8 * P);
+  L.m = take(8 * P);
+  L.I = take(8 * P);
+  L.mode = take(4 * P);
+  L.presc = take(48 * P);
+  L.tpresc = take(8 * P);
+  L.Fprev = take(48 * P);
+  L.prev_valid = take(4 * P);
+  L.Ffp = take(48 * P);
+  L.Fraw = take(48 * P);
+  L.Fold = take(48 * P);
+  L.old_valid = take(4 * P);
+  L.diag = take(144 * P);
+  L.Fnew = take(48 * P);
+  L.hist_id = take(4 * P * HIST_SLOTS);
+  L.hist_d = take(24 * P * HIST_SLOTS);
+  L.nbr = take(4 * P * NBR_MAX);
+  L.nbr_n = take(4 * P);
+  L.partial = take(48 * P * (size_t)zblocks(c));
+  L.status = take(256);
+  L.total = o;
+  return L;
+}
+
+const char* check_config(const lbmdem_config* c) {
+  if (!c) return "config is NULL";
+  if (c->nx < 4 || c->ny < 4 || c->nz < 4) return "lattice must be at least 4 cells per axis";
+  if ((double)c->nx * c->ny * c->nz >= 2147483647.0) return "lattice exceeds 2^31 cells";
+  for (int a = 0; a < 3; ++a)
+    if (c->walls[a] != 0 && c->walls[a] != 1) return "walls[] must be 0 or 1";
+  if (!(c->nu > 0.0)) return "nu must be positive";
+  if (!(c->magic_lambda > 0.0) || !(c->lambda_b > 0.0)) return "Lambda and Lambda_b must be positive";
+  if (!(c->delta_ab >= 0.0)) return "delta_ab must be non-negative";
+  if (c->collision < 0 || c->collision > 3) return "collision must be 0..3";
+  if (c->boundary < 0 || c->boundary > 1) return "boundary must be 0 or 1";
+  if (c->storage < 0 || c->storage > 2) return "storage must be 0..2";
+  if (c->n_sub < 1) return "n_sub must be >= 1";
+  if (c->max_spheres < 0) return "max_spheres must be >= 0";
+  if (c->max_spheres > 0 && !(c->max_radius > 0.0)) return "max_radius must be positive";
+  if (!(c->e_dry > 0.0 && c->e_dry <= 1.0)) return "e_dry must lie in (0, 1]";
+  if (!(c->poisson_ratio >= 0.0 && c->poisson_ratio < 1.0)) return "poisson_ratio must lie in [0, 1)";
+  if (!(c->friction >= 0.0)) return "friction must be non-negative";
+  if (!(c->cut_n > 0.0 && c->cut_tt > 0.0 && c->cut_tr > 0.0)) return "cut-offs must be positive";
+  return nullptr;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct lbmdem_domain {
+  lbmdem_config cfg;
+  DevDomain d;
+  Layout L;
+  hipStream_t stream = nullptr;
+  void* region = nullptr;
+  bool owns = false;
+  int cur = 0;
+  uint32_t stamp = 0;
+  int64_t steps = 0;
+  int failed = 0;
+  std::string err;
+  std::vector<double> hx, hR;  // host shadow for insertion checks
+  bool prof = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Ev> pending;
+  std::vector<hipEvent_t> spare;
+  double ms[3] = {0, 0, 0};
+  int64_t cnt[3] = {0, 0, 0};
+};
+
+static int32_t fail(lbmdem_domain* dom, int32_t code, const std::string& msg) {
+  if (dom) dom->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(dom, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(dom, LBMDEM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static hipEvent_t get_event(lbmdem_domain* dom) {
+  if (!dom->spare.empty()) {
+    hipEvent_t e = dom->spare.back();
+    dom->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void harvest(lbmdem_domain* dom) {
+  for (auto& e : dom->pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+      dom->ms[e.kind] += t;
+      dom->cnt[e.kind] += 1;
+    }
+    dom->spare.push_back(e.a);
+    dom->spare.push_back(e.b);
+  }
+  dom->pending.clear();
+}
+
+template <typename F>
+static void timed(lbmdem_domain* dom, int kind, F&& launch) {
+  if (!dom->prof) {
+    launch();
+    return;
+  }
+  if (dom->pending.size() > 4096) {
+    (void)hipStreamSynchronize(dom->stream);
+    harvest(dom);
+  }
+  lbmdem_domain::Ev ev{get_event(dom), get_event(dom), kind};
+  if (ev.a) (void)hipEventRecord(ev.a, dom->stream);
+  launch();
+  if (ev.b) (void)hipEventRecord(ev.b, dom->stream);
+  if (ev.a && ev.b) dom->pending.push_back(ev);
+}
+
+static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
+  dom->stamp += 1;
+  dom->d.P = (int)dom->hR.size();
+  timed(dom, 2, [&] { launch_mapping(dom->d, dom->cur, dom->stamp, reconstruct, dom->stream); });
+  HIPCHK(dom, hipGetLastError());
+  return LBMDEM_OK;
+}
+
+extern "C" {
+
+int32_t lbmdem_config_init(lbmdem_config* c) {
+  if (!c) return LBMDEM_EINVAL;
+  std::memset(c, 0, sizeof(*c));
+  c->nx = c->ny = c->nz = 32;
+  c->walls[2] = 1;
+  c->nu = 0.01;
+  c->magic_lambda = 3.0 / 16.0;
+  c->lambda_b = 100.0;
+  c->delta_ab = 2.0;
+  c->collision = LBMDEM_TRT_AB;
+  c->boundary = LBMDEM_BC_CLI;
+  c->storage = LBMDEM_STORE_F32;
+  c->n_sub = 10;
+  c->force_averaging = 1;
+  c->e_dry = 0.97;
+  c->poisson_ratio = 0.23;
+  c->friction = 0.15;
+  c->tc = -1.0;
+  c->dmin = -1.0;
+  c->cut_n = 2.0 / 3.0;
+  c->cut_tt = 0.5;
+  c->cut_tr = 0.5;
+  c->lub_mask = 7;
+  c->max_spheres = 16;
+  c->max_radius = 12.0;
+  return LBMDEM_OK;
+}
+
+size_t lbmdem_footprint_bytes(const lbmdem_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return make_layout(*cfg).total;
+}
+
+int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes, void* hip_stream,
+                      lbmdem_domain** out) {
+  if (!out) return fail(nullptr, LBMDEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* e = check_config(cfg)) return fail(nullptr, LBMDEM_EINVAL, e);
+  Layout L = make_layout(*cfg);
+  if (dev_buf && dev_bytes < L.total)
+    return fail(nullptr, LBMDEM_ENOMEM, "device region smaller than lbmdem_footprint_bytes()");
+  if (dev_buf && ((uintptr_t)dev_buf & 255))
+    return fail(nullptr, LBMDEM_EINVAL, "device region must be 256-byte aligned");
+  lbmdem_domain* dom = new (std::nothrow) lbmdem_domain();
+  if (!dom) return fail(nullptr, LBMDEM_ENOMEM, "host allocation failed");
+  dom->cfg = *cfg;
+  dom->L = L;
+  dom->stream = (hipStream_t)hip_stream;
+  if (dev_buf) {
+    dom->region = dev_buf;
+  } else {
+    if (hipMalloc(&dom->region, L.total) != hipSuccess) {
+      delete dom;
+      return fail(nullptr, LBMDEM_ENOMEM, "hipMalloc of the domain region failed");
+    }
+    dom->owns = true;
+  }
+  char* base = (char*)dom->region;
+  DevDomain& d = dom->d;
+  std::memset(&d, 0, sizeof(d));
+  d.nx = cfg->nx;
+  d.ny = cfg->ny;
+  d.nz = cfg->nz;
+  d.N = (long long)cfg->nx * cfg->ny * cfg->nz;
+  for (int a = 0; a < 3; ++a) {
+    d.walls[a] = cfg->walls[a];
+    d.wall_u_lo[a] = cfg->wall_u_lo[a];
+    d.wall_u_hi[a] = cfg->wall_u_hi[a];
+    d.gravity[a] = cfg->gravity[a];
+  }
+  d.storage = cfg->storage;
+  d.boundary = cfg->boundary;
+  // Eq. (Viscosity), Eq. (MagicParameter), Eq. (lambda_b)
+  const double snu = 1.0 / (3.0 * cfg->nu + 0.5);
+  const double tau = 1.0 / snu - 0.5;
+  const double smi = 1.0 / (0.5 + cfg->magic_lambda / tau);
+  const double sb = 1.0 / (0.5 + cfg->lambda_b * tau);
+  d.s_nu = snu;
+  d.s_plus = snu;
+  d.s_minus = smi;
+  switch (cfg->collision) {
+    case LBMDEM_TRT_AB: d.s_bulk_shell = sb; d.s_bulk_other = snu; break;
+    case LBMDEM_TRT_B: d.s_bulk_shell = sb; d.s_bulk_other = sb; break;
+    case LBMDEM_TRT: d.s_bulk_shell = snu; d.s_bulk_other = snu; break;
+    default: d.s_minus = snu; d.s_bulk_shell = snu; d.s_bulk_other = snu; break;
+  }
+  d.delta_ab = cfg->delta_ab;
+  d.pdf[0] = base + L.pdf0;
+  d.pdf[1] = base + L.pdf1;
+  d.flags = (uint8_t*)(base + L.flags);
+  d.owner = (int32_t*)(base + L.owner);
+  d.claim = (unsigned long long*)(base + L.claim);
+  d.shellstamp = (uint32_t*)(base + L.shellstamp);
+  DevParticles& p = d.p;
+  p.x = (double*)(base + L.x);
+  p.u = (double*)(base + L.u);
+  p.w = (double*)(base + L.w);
+  p.xmap = (double*)(base + L.xmap);
+  p.R = (double*)(base + L.R);
+  p.rho = (double*)(base + L.rho);
+  p.m = (double*)(base + L.m);
+  p.I = (double*)(base + L.I);
+  p.mode = (int*)(base + L.mode);
+  p.presc = (double*)(base + L.presc);
+  p.tpresc = (double*)(base + L.tpresc);
+  p.Fprev = (double*)(base + L.Fprev);
+  p.prev_valid = (int*)(base + L.prev_valid);
+  p.Ffp = (double*)(base + L.Ffp);
+  p.Fraw = (double*)(base + L.Fraw);
+  p.Fold = (double*)(base + L.Fold);
+  p.old_valid = (int*)(base + L.old_valid);
+  p.diag = (double*)(base + L.diag);
+  p.Fnew = (double*)(base + L.Fnew);
+  p.hist_id = (int*)(base + L.hist_id);
+  p.hist_d = (double*)(base + L.hist_d);
+  p.nbr = (int*)(base + L.nbr);
+  p.nbr_n = (int*)(base + L.nbr_n);
+  d.P = 0;
+  d.ZB = zblocks(*cfg);
+  d.partial = (double*)(base + L.partial);
+  d.status = (int*)(base + L.status);
+  d.n_sub = cfg->n_sub;
+  d.force_averaging = cfg->force_averaging;
+  d.e_dry = cfg->e_dry;
+  d.poisson_ratio = cfg->poisson_ratio;
+  d.friction = cfg->friction;
+  d.tc = cfg->tc;
+  d.dmin = cfg->dmin;
+  d.cut_n = cfg->cut_n;
+  d.cut_tt = cfg->cut_tt;
+  d.cut_tr = cfg->cut_tr;
+  d.lub_mask = cfg->lub_mask;
+  d.nu = cfg->nu;
+  d.skin = 1.0;
+  hipStream_t s = dom->stream;
+  const size_t Pm = (size_t)std::max(cfg->max_spheres, 1);
+  // particle block and status are plain zeros except the free history slots
+  int32_t rc = LBMDEM_OK;
+  if (hipMemsetAsync(base + L.x, 0, L.total - L.x, s) != hipSuccess ||
+      hipMemsetD32Async((hipDeviceptr_t)(base + L.hist_id), (int)0x80000000, Pm * HIST_SLOTS, s) !=
+          hipSuccess)
+    rc = fail(nullptr, LBMDEM_EDEVICE, "initialising the particle block failed");
+  if (rc == LBMDEM_OK) {
+    launch_fill_claims(d, s);
+    if (hipGetLastError() != hipSuccess) rc = fail(nullptr, LBMDEM_EDEVICE, "init kernel launch failed");
+  }
+  if (rc == LBMDEM_OK && remap(dom, false) != LBMDEM_OK)
+    rc = fail(nullptr, LBMDEM_EDEVICE, dom->err);
+  if (rc == LBMDEM_OK && hipStreamSynchronize(s) != hipSuccess)
+    rc = fail(nullptr, LBMDEM_EDEVICE, "initialisation failed on the device");
+  if (rc != LBMDEM_OK) {
+    if (dom->owns) (void)hipFree(dom->region);
+    delete dom;
+    return rc;
+  }
+  *out = dom;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_destroy(lbmdem_domain* dom) {
+  if (!dom) return LBMDEM_OK;
+  (void)hipStreamSynchronize(dom->stream);
+  harvest(dom);
+  for (auto e : dom->spare) (void)hipEventDestroy(e);
+  if (dom->owns) (void)hipFree(dom->region);
+  delete dom;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_num_spheres(const lbmdem_domain* dom) { return dom ? (int32_t)dom->hR.size() : -1; }
+
+static double min_wall_gap_h(const lbmdem_config& c, const double* x, double R) {
+  const int n[3] = {c.nx, c.ny, c.nz};
+  double g = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    if (!c.walls[a]) continue;
+    g = std::min(g, (x[a] - 1.0) - R);
+    g = std::min(g, (((double)n[a] - 1.0) - x[a]) - R);
+  }
+  return g;
+}
+
+static double min_img_h(const lbmdem_config& c, int a, double v) {
+  const int n[3] = {c.nx, c.ny, c.nz};
+  if (c.walls[a]) return v;
+  const double L = (double)n[a];
+  if (v > 0.5 * L) return v - L;
+  if (v < -0.5 * L) return v + L;
+  return v;
+}
+
+static int32_t refresh_host_positions(lbmdem_domain* dom) {
+  const size_t P = dom->hR.size();
+  dom->hx.resize(3 * P);
+  if (P) HIPCHK(dom, hipMemcpyAsync(dom->hx.data(), dom->d.p.x, 24 * P, hipMemcpyDeviceToHost, dom->stream));
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_add_spheres(lbmdem_domain* dom, int32_t n, const double* x, const double* u,
+                           const double* w, const double* radius, const double* rho,
+                           int32_t* ids_out) {
+  if (!dom) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  if (n < 0 || (n > 0 && (!x || !radius || !rho))) return fail(dom, LBMDEM_EINVAL, "bad arguments");
+  if (n == 0) return LBMDEM_OK;
+  const lbmdem_config& c = dom->cfg;
+  const size_t P0 = dom->hR.size();
+  if ((long long)P0 + n > c.max_spheres) return fail(dom, LBMDEM_ECAPACITY, "max_spheres exceeded");
+  if (int32_t rc = refresh_host_positions(dom)) return rc;
+  const int nn[3] = {c.nx, c.ny, c.nz};
+  std::vector<double> ax(dom->hx), aR(dom->hR);
+  for (int s = 0; s < n; ++s) {
+    const double* xs = x + 3 * s;
+    const double R = radius[s];
+    if (!(R > 0.0) || R > c.max_radius || !(rho[s] > 0.0))
+      return fail(dom, LBMDEM_EINVAL, "radius must lie in (0, max_radius] and density be positive");
+    for (int a = 0; a < 3; ++a)
+      if (!(xs[a] >= 0.0 && xs[a] < (double)nn[a]))
+        return fail(dom, LBMDEM_EINVAL, "sphere centre outside the lattice");
+    if (min_wall_gap_h(c, xs, R) < 0.0) return fail(dom, LBMDEM_EOVERLAP, "sphere crosses a wall plane");
+    for (size_t j = 0; j < aR.size(); ++j) {
+      double dd[3];
+      for (int a = 0; a < 3; ++a) dd[a] = min_img_h(c, a, xs[a] - ax[3 * j + a]);
+      const double dist = std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      if (dist - (R + aR[j]) < 0.0) return fail(dom, LBMDEM_EOVERLAP, "spheres overlap");
+    }
+    for (int a = 0; a < 3; ++a) ax.push_back(xs[a]);
+    aR.push_back(R);
+  }
+  std::vector<double> hu(3 * n, 0.0), hw(3 * n, 0.0), hm(n), hI(n);
+  for (int s = 0; s < n; ++s) {
+    for (int a = 0; a < 3; ++a) {
+      if (u) hu[3 * s + a] = u[3 * s + a];
+      if (w) hw[3 * s + a] = w[3 * s + a];
+    }
+    const double R = radius[s];
+    hm[s] = rho[s] * (4.0 / 3.0) * PI_H * R * R * R;
+    hI[s] = 0.4 * hm[s] * R * R;
+  }
+  DevParticles& p = dom->d.p;
+  hipStream_t st = dom->stream;
+  HIPCHK(dom, hipMemcpyAsync(p.x + 3 * P0, x, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.xmap + 3 * P0, x, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.u + 3 * P0, hu.data(), 24 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.w + 3 * P0, hw.data(), 24 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.R + P0, radius, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.rho + P0, rho, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.m + P0, hm.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.I + P0, hI.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipStreamSynchronize(st));
+  for (int s = 0; s < n; ++s) {
+    dom->hR.push_back(radius[s]);
+    if (ids_out) ids_out[s] = (int32_t)(P0 + s);
+  }
+  return remap(dom, true);
+}
+
+// positions the next mapping starts from = current positions
+static int32_t pin_mapped_positions(lbmdem_domain* dom) {
+  const size_t P = dom->hR.size();
+  if (P) launch_copy(dom->d.p.xmap, dom->d.p.x, 24 * P, dom->stream);
+  HIPCHK(dom, hipGetLastError());
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_update_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, const double* x,
+                              const double* u, const double* w, int32_t mask) {
+  if (!dom) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  if (n < 0 || (n > 0 && !ids)) return fail(dom, LBMDEM_EINVAL, "bad arguments");
+  if (((mask & 1) && !x) || ((mask & 2) && !u) || ((mask & 4) && !w))
+    return fail(dom, LBMDEM_EINVAL, "masked field pointer is NULL");
+  const int nn[3] = {dom->cfg.nx, dom->cfg.ny, dom->cfg.nz};
+  for (int s = 0; s < n; ++s) {
+    if (ids[s] < 0 || ids[s] >= (int32_t)dom->hR.size()) return fail(dom, LBMDEM_EINVAL, "bad sphere id");
+    if (mask & 1)
+      for (int a = 0; a < 3; ++a)
+        if (!(x[3 * s + a] >= 0.0 && x[3 * s + a] < (double)nn[a]))
+          return fail(dom, LBMDEM_EINVAL, "sphere centre outside the lattice");
+  }
+  if (int32_t rc = pin_mapped_positions(dom)) return rc;
+  DevParticles& p = dom->d.p;
+  hipStream_t st = dom->stream;
+  const int zero = 0;
+  for (int s = 0; s < n; ++s) {
+    const int i = ids[s];
+    if (mask & 1) HIPCHK(dom, hipMemcpyAsync(p.x + 3 * i, x + 3 * s, 24, hipMemcpyHostToDevice, st));
+    if (mask & 2) HIPCHK(dom, hipMemcpyAsync(p.u + 3 * i, u + 3 * s, 24, hipMemcpyHostToDevice, st));
+    if (mask & 4) HIPCHK(dom, hipMemcpyAsync(p.w + 3 * i, w + 3 * s, 24, hipMemcpyHostToDevice, st));
+    HIPCHK(dom, hipMemcpyAsync(p.old_valid + i, &zero, 4, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(dom, hipStreamSynchronize(st));
+  return remap(dom, true);
+}
+
+int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, const double* u_target,
+                               double c_acc, double t_st, double release_gap) {
+  if (!dom) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  if (id < 0 || id >= (int32_t)dom->hR.size() || mode < 0 || mode > 2)
+    return fail(dom, LBMDEM_EINVAL, "bad sphere id or mode");
+  if (mode == LBMDEM_PRESCRIBED && (!u_target || !(t_st > 0.0)))
+    return fail(dom, LBMDEM_EINVAL, "prescribed mode needs u_target and t_st > 0");
+  if (int32_t rc = pin_mapped_positions(dom)) return rc;
+  DevParticles& p = dom->d.p;
+  hipStream_t st = dom->stream;
+  const int zero = 0;
+  HIPCHK(dom, hipMemcpyAsync(p.mode + id, &mode, 4, hipMemcpyHostToDevice, st));
+  HIPCHK(dom, hipMemcpyAsync(p.old_valid + id, &zero, 4, hipMemcpyHostToDevice, st));
+  if (mode == LBMDEM_PRESCRIBED) {
+    const double pr[6] = {u_target[0], u_target[1], u_target[2], c_acc, t_st, release_gap};
+    const double z3[3] = {0, 0, 0};
+    const double t0 = 0.0;
+    HIPCHK(dom, hipMemcpyAsync(p.presc + 6 * id, pr, 48, hipMemcpyHostToDevice, st));
+    HIPCHK(dom, hipMemcpyAsync(p.tpresc + id, &t0, 8, hipMemcpyHostToDevice, st));
+    HIPCHK(dom, hipMemcpyAsync(p.u + 3 * id, z3, 24, hipMemcpyHostToDevice, st));
+    HIPCHK(dom, hipMemcpyAsync(p.w + 3 * id, z3, 24, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(dom, hipStreamSynchronize(st));
+  return remap(dom, true);
+}
+
+int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
+  if (!dom || nsteps < 0) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  for (int s = 0; s < nsteps; ++s) {
+    timed(dom, 0, [&] { launch_sweep(dom->d, dom->cur, dom->stream); });
+    dom->cur ^= 1;
+    timed(dom, 1, [&] { launch_dem(dom->d, dom->stream); });
+    if (int32_t rc = remap(dom, true)) return rc;
+    dom->steps += 1;
+  }
+  HIPCHK(dom, hipGetLastError());
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_sync(lbmdem_domain* dom) {
+  if (!dom) return LBMDEM_EINVAL;
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  int st = 0;
+  HIPCHK(dom, hipMemcpy(&st, dom->d.status, 4, hipMemcpyDeviceToHost));
+  if (st & ST_NONFINITE) {
+    dom->failed = 1;
+    return fail(dom, LBMDEM_EUNSTABLE, "non-finite particle state");
+  }
+  if (st & (ST_HIST_FULL | ST_NBR_FULL)) {
+    dom->failed = 1;
+    return fail(dom, LBMDEM_ECAPACITY, "contact-history or neighbour slots exhausted");
+  }
+  return dom->failed ? LBMDEM_ESTATE : LBMDEM_OK;
+}
+
+int32_t lbmdem_get_sphere_state(lbmdem_domain* dom, int32_t id, double* out) {
+  if (!dom || !out) return LBMDEM_EINVAL;
+  if (id < 0 || id >= (int32_t)dom->hR.size()) return fail(dom, LBMDEM_EINVAL, "bad sphere id");
+  const DevParticles& p = dom->d.p;
+  hipStream_t st = dom->stream;
+  double ffp[6], dg[18], fr[6], rr[2];
+  int mode = 0;
+  HIPCHK(dom, hipMemcpyAsync(out + 0, p.x + 3 * id, 24, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(out + 3, p.u + 3 * id, 24, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(out + 6, p.w + 3 * id, 24, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(ffp, p.Ffp + 6 * id, 48, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(dg, p.diag + 18 * id, 144, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(fr, p.Fraw + 6 * id, 48, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(&mode, p.mode + id, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(&rr[0], p.R + id, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipMemcpyAsync(&rr[1], p.rho + id, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipStreamSynchronize(st));
+  for (int k = 0; k < 6; ++k) out[9 + k] = ffp[k];
+  for (int k = 0; k < 18; ++k) out[15 + k] = dg[k];
+  out[33] = (double)mode;
+  out[34] = rr[0];
+  out[35] = rr[1];
+  for (int k = 0; k < 6; ++k) out[36 + k] = fr[k];
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t bytes,
+                         int32_t dst_is_device) {
+  if (!dom || !dst) return LBMDEM_EINVAL;
+  const size_t N = (size_t)dom->d.N;
+  size_t need = 0;
+  int first = 0, planes = 0;
+  switch (field) {
+    case LBMDEM_FIELD_RHO: need = 8 * N; first = 0; planes = 1; break;
+    case LBMDEM_FIELD_VEL: need = 24 * N; first = 1; planes = 3; break;
+    case LBMDEM_FIELD_PDF: need = 8 * N * Q; first = 10; planes = Q; break;
+    case LBMDEM_FIELD_FLAGS: need = N; first = 40; planes = 1; break;
+    case LBMDEM_FIELD_OWNER: need = 4 * N; first = 41; planes = 1; break;
+    default: return fail(dom, LBMDEM_EINVAL, "unknown field");
+  }
+  if (bytes < need) return fail(dom, LBMDEM_EINVAL, "destination too small");
+  double* stage = (double*)((char*)dom->region + dom->L.stage);
+  hipStream_t st = dom->stream;
+  const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (field == LBMDEM_FIELD_FLAGS || field == LBMDEM_FIELD_OWNER) {
+    std::vector<double> h(N);
+    launch_fields(dom->d, dom->cur, first, stage, st);
+    HIPCHK(dom, hipGetLastError());
+    HIPCHK(dom, hipMemcpyAsync(h.data(), stage, 8 * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(dom, hipStreamSynchronize(st));
+    if (field == LBMDEM_FIELD_FLAGS) {
+      std::vector<uint8_t> o(N);
+      for (size_t c = 0; c < N; ++c) o[c] = (uint8_t)h[c];
+      HIPCHK(dom, hipMemcpy(dst, o.data(), N, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    } else {
+      std::vector<int32_t> o(N);
+      for (size_t c = 0; c < N; ++c) o[c] = (int32_t)h[c];
+      HIPCHK(dom, hipMemcpy(dst, o.data(), 4 * N, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    }
+    return LBMDEM_OK;
+  }
+  for (int k = 0; k < planes; ++k) {
+    launch_fields(dom->d, dom->cur, first + k, stage, st);
+    HIPCHK(dom, hipGetLastError());
+    HIPCHK(dom, hipMemcpyAsync((char*)dst + 8 * N * (size_t)k, stage, 8 * N, kind, st));
+    HIPCHK(dom, hipStreamSynchronize(st));
+  }
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
+  if (!dom || !f) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  const size_t N = (size_t)dom->d.N;
+  double* stage = (double*)((char*)dom->region + dom->L.stage);
+  hipStream_t st = dom->stream;
+  for (int q = 0; q < Q; ++q) {
+    HIPCHK(dom, hipMemcpyAsync(stage, f + (size_t)q * N, 8 * N, hipMemcpyHostToDevice, st));
+    launch_set_pdf(dom->d, dom->cur + 2 * q, stage, st);
+    HIPCHK(dom, hipGetLastError());
+    HIPCHK(dom, hipStreamSynchronize(st));
+  }
+  if (int32_t rc = pin_mapped_positions(dom)) return rc;
+  return remap(dom, false);
+}
+
+int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable) {
+  if (!dom) return LBMDEM_EINVAL;
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  harvest(dom);
+  dom->prof = enable != 0;
+  for (int k = 0; k < 3; ++k) {
+    dom->ms[k] = 0.0;
+    dom->cnt[k] = 0;
+  }
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_get_profile(lbmdem_domain* dom, int32_t kernel, double* total_ms, int64_t* count) {
+  if (!dom || kernel < 0 || kernel > 2) return LBMDEM_EINVAL;
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  harvest(dom);
+  if (total_ms) *total_ms = dom->ms[kernel];
+  if (count) *count = dom->cnt[kernel];
+  return LBMDEM_OK;
+}
+
+double lbmdem_sweep_bytes(const lbmdem_domain* dom) {
+  if (!dom) return 0.0;
+  return (2.0 * Q * (double)storage_size(dom->cfg.storage) + 1.0) * (double)dom->d.N;
+}
+
+int32_t lbmdem_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src) return LBMDEM_EINVAL;
+  launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? LBMDEM_OK : LBMDEM_EDEVICE;
+}
+
+const char* lbmdem_last_error(const lbmdem_domain* dom) {
+  return dom ? dom->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

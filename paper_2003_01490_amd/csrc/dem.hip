@@ -1,0 +1,397 @@
+// Discrete element part of one time step (Alg. 1, DEM sub-cycles), FP64.
+//
+// Prologue: per-sphere sum of the momentum-exchange partials written by the
+// boundary kernel (fixed order: slab blocks ascending), averaging with the
+// previous step (Sec. 4.2; the first step averages with itself), copy of the
+// positions the mapping starts from, and a neighbour list per sphere
+// (candidates whose gap is below the largest lubrication cut-off plus a skin).
+// Then n_sub sub-cycles with dt_p = 1/n_sub and F_fp held constant:
+//   release of prescribed spheres below their gap; velocity-Verlet start force
+//   for newly free spheres; Eq. (velocity_verlet_1); lubrication (Sec. 3.1,
+//   step function on the raw gap, magnitude on max(gap, delta_min)), contacts
+//   (Eqs. normalCollisionForce, tangentialCollisionForce with the spring
+//   projected, rescaled and reset as in Sec. 4.1.2), external force
+//   V (rho_p - rho_f) g; Eq. (velocity_verlet_2) and its rotational analogue.
+// Forces are gathered per sphere (each sphere sums over its own partners), so
+// nothing is scattered and the pair terms come out antisymmetric exactly.
+// One workgroup; the sub-cycles are separated by workgroup barriers.
+#include "internal.hpp"
+
+#include <climits>
+
+namespace lbmdem {
+
+constexpr double PI_D = 3.14159265358979323846;
+
+struct Partner {
+  int code;        // sphere id >= 0, wall -1 - (2 axis + side)
+  int j;           // sphere id or -1
+  double n[3];     // unit normal from partner to i
+  double delta;    // signed gap
+  double xcp[3];   // contact point
+  double rj[3];    // xcp - x_j
+};
+
+__device__ inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+__device__ inline double norm3(const double* a) { return sqrt(dot3(a, a)); }
+
+// rigid-body surface velocity u + w x r (r = point - centre)
+__device__ inline void body_vel(const double* u, const double* w, const double* r, double* U) {
+  double wr[3];
+  cross3(w, r, wr);
+  U[0] = u[0] + wr[0];
+  U[1] = u[1] + wr[1];
+  U[2] = u[2] + wr[2];
+}
+
+__device__ inline double min_wall_gap(const DevDomain& d, int i) {
+  double g = 1e300;
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (!d.walls[a]) continue;
+    const double lo = (d.p.x[3 * i + a] - 1.0) - d.p.R[i];
+    const double hi = (((double)n[a] - 1.0) - d.p.x[3 * i + a]) - d.p.R[i];
+    g = fmin(g, fmin(lo, hi));
+  }
+  return g;
+}
+
+__device__ inline void make_sphere_partner(const DevDomain& d, int i, int j, Partner& pt) {
+  double dd[3];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int a = 0; a < 3; ++a) dd[a] = min_image(d.p.x[3 * i + a] - d.p.x[3 * j + a], n[a], d.walls[a]);
+  const double dist = norm3(dd);
+  pt.code = j;
+  pt.j = j;
+  for (int a = 0; a < 3; ++a) pt.n[a] = dd[a] / dist;
+  pt.delta = dist - (d.p.R[i] + d.p.R[j]);
+  for (int a = 0; a < 3; ++a) {
+    pt.xcp[a] = d.p.x[3 * i + a] - 0.5 * dd[a];
+    pt.rj[a] = 0.5 * dd[a];
+  }
+}
+
+__device__ inline void make_wall_partner(const DevDomain& d, int i, int a, int side, Partner& pt) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+  pt.code = -1 - (2 * a + side);
+  pt.j = -1;
+  pt.n[0] = pt.n[1] = pt.n[2] = 0.0;
+  pt.n[a] = side ? -1.0 : 1.0;
+  const double R = d.p.R[i];
+  const double xa = d.p.x[3 * i + a];
+  pt.delta = side ? (((double)n[a] - 1.0) - xa) - R : (xa - 1.0) - R;
+  for (int b = 0; b < 3; ++b) pt.xcp[b] = d.p.x[3 * i + b] - (R + 0.5 * pt.delta) * pt.n[b];
+  pt.rj[0] = pt.rj[1] = pt.rj[2] = 0.0;
+}
+
+__device__ inline double collision_time(const DevDomain& d, double D) {
+  return d.tc > 0.0 ? d.tc : 2.31 * D * sqrt(3.0);  // Eq. (collisionTimeChoice)
+}
+__device__ inline double min_lub_gap(const DevDomain& d, double R) {
+  return d.dmin >= 0.0 ? d.dmin : (0.001 + 0.00007 * R) * R;  // Eq. (lubricationGapSize)
+}
+
+__device__ void lubrication(const DevDomain& d, double dmin, const double* n, double delta,
+                            const double* ui, const double* wi, double Ri, const double* uj,
+                            const double* wj, double Rj, bool wall, double* F, double* T) {
+  const double mu = d.nu;
+  const double dl = delta > dmin ? delta : dmin;
+  double uij[3], un[3], ut[3];
+  for (int a = 0; a < 3; ++a) uij[a] = ui[a] - (wall ? 0.0 : uj[a]);
+  const double uijn = dot3(uij, n);
+  for (int a = 0; a < 3; ++a) {
+    un[a] = uijn * n[a];
+    ut[a] = uij[a] - un[a];
+  }
+  const double k = wall ? 0.0 : Rj / Ri;
+  if ((d.lub_mask & 1) && delta > 0.0 && delta < d.cut_n) {
+    const double coef = wall ? 1.0 : (k * k) / ((1.0 + k) * (1.0 + k));
+    const double mag = -6.0 * PI_D * mu * Ri * Ri * coef * (1.0 / dl - 1.0 / d.cut_n);
+    for (int a = 0; a < 3; ++a) F[a] += mag * un[a];
+  }
+  if ((d.lub_mask & 2) && delta > 0.0 && delta < d.cut_tt) {
+    const double L = log(dl / d.cut_tt);
+    const double cf = wall ? 8.0 / 15.0
+                           : 4.0 * k * (2.0 + k + 2.0 * k * k) / (15.0 * (1.0 + k) * (1.0 + k) * (1.0 + k));
+    const double ct = wall ? 0.1 : k * (4.0 + k) / (10.0 * (1.0 + k) * (1.0 + k));
+    const double fm = 6.0 * PI_D * mu * Ri * cf * L;
+    const double tm = 8.0 * PI_D * mu * Ri * Ri * ct * L;
+    double uxn[3];
+    cross3(uij, n, uxn);
+    for (int a = 0; a < 3; ++a) {
+      F[a] += fm * ut[a];
+      T[a] += tm * uxn[a];
+    }
+  }
+  if ((d.lub_mask & 4) && delta > 0.0 && delta < d.cut_tr) {
+    const double L = log(dl / d.cut_tr);
+    const double cf = wall ? 2.0 / 15.0 : 2.0 * k * k / (15.0 * (1.0 + k) * (1.0 + k));
+    const double ct = wall ? 0.4 : 2.0 * k / (5.0 * (1.0 + k));
+    double wv[3], av[3], wxn[3];
+    for (int a = 0; a < 3; ++a) {
+      wv[a] = wall ? wi[a] : (wi[a] + wj[a]) + (4.0 / k) * wi[a] + 4.0 * k * wj[a];
+      av[a] = wall ? wi[a] : wi[a] + 0.25 * k * wj[a];
+    }
+    cross3(wv, n, wxn);
+    const double an = dot3(av, n);
+    const double fm = -6.0 * PI_D * mu * Ri * Ri * cf * L;
+    const double tm = 8.0 * PI_D * mu * Ri * Ri * Ri * ct * L;
+    for (int a = 0; a < 3; ++a) {
+      F[a] += fm * wxn[a];
+      T[a] += tm * (av[a] - an * n[a]);
+    }
+  }
+}
+
+// forces on sphere i at the current state; contact: evaluate contacts;
+// upd: write the tangential-spring history
+__device__ void eval_forces(const DevDomain& d, int i, bool contact, bool upd, double dtp,
+                            double* Fout, double* Tout) {
+  const DevParticles& p = d.p;
+  double Flub[3] = {0, 0, 0}, Tlub[3] = {0, 0, 0}, Fcol[3] = {0, 0, 0}, Tcol[3] = {0, 0, 0};
+  const double maxcut = fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr));
+  const double* xi = p.x + 3 * i;
+  const double* ui = p.u + 3 * i;
+  const double* wi = p.w + 3 * i;
+  const double Ri = p.R[i];
+  int* hid = p.hist_id + (size_t)i * HIST_SLOTS;
+  double* hd = p.hist_d + (size_t)i * HIST_SLOTS * 3;
+  const int nn = p.nbr_n[i];
+  const int nwalls = 2 * (d.walls[0] + d.walls[1] + d.walls[2]);
+  const double zero[3] = {0, 0, 0};
+  for (int pi = 0; pi < nn + nwalls; ++pi) {
+    Partner pt;
+    if (pi < nn) {
+      make_sphere_partner(d, i, p.nbr[(size_t)i * NBR_MAX + pi], pt);
+    } else {
+      int wk = pi - nn, a = 0;
+      for (a = 0; a < 3; ++a) {
+        if (!d.walls[a]) continue;
+        if (wk < 2) break;
+        wk -= 2;
+      }
+      make_wall_partner(d, i, a, wk, pt);
+    }
+    const bool is_wall = pt.j < 0;
+    const double* uj = is_wall ? zero : p.u + 3 * pt.j;
+    const double* wj = is_wall ? zero : p.w + 3 * pt.j;
+    const double Rj = is_wall ? 0.0 : p.R[pt.j];
+    int slot = -1;
+    for (int s = 0; s < HIST_SLOTS; ++s)
+      if (hid[s] == pt.code) slot = s;
+    if (contact && pt.delta < 0.0) {
+      double uij[3], un[3], Ui[3], Uj[3], ut[3], ri[3];
+      for (int a = 0; a < 3; ++a) {
+        uij[a] = ui[a] - uj[a];
+        ri[a] = pt.xcp[a] - xi[a];
+      }
+      const double uijn = dot3(uij, pt.n);
+      for (int a = 0; a < 3; ++a) un[a] = uijn * pt.n[a];
+      body_vel(ui, wi, ri, Ui);
+      if (is_wall) {
+        Uj[0] = Uj[1] = Uj[2] = 0.0;
+      } else {
+        body_vel(uj, wj, pt.rj, Uj);
+      }
+      for (int a = 0; a < 3; ++a) ut[a] = (Ui[a] - Uj[a]) - un[a];
+      const double mi = p.m[i];
+      const double meff = is_wall ? mi : mi * p.m[pt.j] / (mi + p.m[pt.j]);
+      const double D = is_wall ? 2.0 * Ri : Ri + Rj;
+      const double Tc = collision_time(d, D);
+      const double le = log(d.e_dry);
+      const double kn = meff * (PI_D * PI_D + le * le) / (Tc * Tc);  // Eq. (normalDEMparameters)
+      const double dn = -2.0 * meff * le / Tc;
+      const double kp = 2.0 * (1.0 - d.poisson_ratio) / (2.0 - d.poisson_ratio);
+      const double kt = kp * kn;  // Eq. (tangentialCollisionParameters)
+      const double dt = sqrt(kp) * dn;
+      double Fn[3];
+      for (int a = 0; a < 3; ++a) Fn[a] = -kn * pt.delta * pt.n[a] - dn * un[a];
+      double hv[3] = {0, 0, 0};
+      if (slot >= 0)
+        for (int a = 0; a < 3; ++a) hv[a] = hd[slot * 3 + a];
+      const double hn = dot3(hv, pt.n);
+      double ht[3];
+      for (int a = 0; a < 3; ++a) ht[a] = hv[a] - hn * pt.n[a];
+      const double lh = norm3(hv), lht = norm3(ht);
+      if (lht > 0.0)
+        for (int a = 0; a < 3; ++a) hv[a] = (lh / lht) * ht[a];
+      else
+        for (int a = 0; a < 3; ++a) hv[a] = ht[a];
+      double Fsd[3];
+      for (int a = 0; a < 3; ++a) Fsd[a] = -kt * hv[a] - dt * ut[a];
+      const double fsd = norm3(Fsd);
+      const double fmax = d.friction * norm3(Fn);
+      double Ft[3], hnew[3];
+      if (fsd < fmax || fsd == 0.0) {
+        for (int a = 0; a < 3; ++a) {
+          Ft[a] = Fsd[a];
+          hnew[a] = hv[a] + dtp * ut[a];
+        }
+      } else {
+        for (int a = 0; a < 3; ++a) {
+          const double tv = Fsd[a] / fsd;
+          Ft[a] = fmax * tv;
+          hnew[a] = -(fmax * tv + dt * ut[a]) / kt;
+        }
+      }
+      double Tt[3];
+      cross3(ri, Ft, Tt);
+      for (int a = 0; a < 3; ++a) {
+        Fcol[a] += Fn[a] + Ft[a];
+        Tcol[a] += Tt[a];
+      }
+      if (upd) {
+        if (slot < 0)
+          for (int s = 0; s < HIST_SLOTS && slot < 0; ++s)
+            if (hid[s] == INT_MIN) slot = s;
+        if (slot < 0) {
+          atomicOr(d.status, ST_HIST_FULL);
+        } else {
+          hid[slot] = pt.code;
+          for (int a = 0; a < 3; ++a) hd[slot * 3 + a] = hnew[a];
+        }
+      }
+    } else if (upd && slot >= 0) {
+      hid[slot] = INT_MIN;
+    }
+    if (pt.delta > 0.0 && pt.delta < maxcut) {
+      const double Rh = is_wall ? Ri : 2.0 * Ri * Rj / (Ri + Rj);
+      lubrication(d, min_lub_gap(d, Rh), pt.n, pt.delta, ui, wi, Ri, uj, wj, Rj, is_wall, Flub, Tlub);
+    }
+  }
+  const double V = (4.0 / 3.0) * PI_D * Ri * Ri * Ri;
+  const double* Ffp = p.Ffp + 6 * i;
+  double* dg = p.diag + 18 * i;
+  for (int a = 0; a < 3; ++a) {
+    const double Fext = V * (p.rho[i] - 1.0) * d.gravity[a];
+    Fout[a] = ((Ffp[a] + Flub[a]) + Fcol[a]) + Fext;
+    Tout[a] = (Ffp[3 + a] + Tlub[a]) + Tcol[a];
+    dg[6 + a] = Flub[a];
+    dg[9 + a] = Tlub[a];
+    dg[12 + a] = Fcol[a];
+    dg[15 + a] = Tcol[a];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dem(DevDomain d) {
+  const int P = d.P;
+  const DevParticles& p = d.p;
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    double F[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < d.ZB; ++b)
+      for (int k = 0; k < 6; ++k) F[k] += d.partial[((size_t)i * d.ZB + b) * 6 + k];
+    for (int k = 0; k < 6; ++k) p.Fraw[6 * i + k] = F[k];
+    if (d.force_averaging) {
+      if (!p.prev_valid[i])
+        for (int k = 0; k < 6; ++k) p.Fprev[6 * i + k] = F[k];
+      for (int k = 0; k < 6; ++k) {
+        p.Ffp[6 * i + k] = 0.5 * (F[k] + p.Fprev[6 * i + k]);
+        p.Fprev[6 * i + k] = F[k];
+      }
+      p.prev_valid[i] = 1;
+    } else {
+      for (int k = 0; k < 6; ++k) p.Ffp[6 * i + k] = F[k];
+    }
+    for (int a = 0; a < 3; ++a) p.xmap[3 * i + a] = p.x[3 * i + a];
+  }
+  // neighbour list for this step, partners ascending
+  const double maxcut = fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr));
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    int cnt = 0;
+    for (int j = 0; j < P; ++j) {
+      if (j == i) continue;
+      double dd[3];
+      for (int a = 0; a < 3; ++a) dd[a] = min_image(p.x[3 * i + a] - p.x[3 * j + a], n[a], d.walls[a]);
+      const double gap = norm3(dd) - (p.R[i] + p.R[j]);
+      if (gap < maxcut + d.skin) {
+        if (cnt < NBR_MAX)
+          p.nbr[(size_t)i * NBR_MAX + cnt] = j;
+        else
+          atomicOr(d.status, ST_NBR_FULL);
+        cnt++;
+      }
+    }
+    p.nbr_n[i] = cnt < NBR_MAX ? cnt : NBR_MAX;
+  }
+  __syncthreads();
+  const double dtp = 1.0 / (double)d.n_sub;
+  for (int sub = 0; sub < d.n_sub; ++sub) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+      if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, i) < p.presc[6 * i + 5]) {
+        p.mode[i] = MODE_FREE;
+        p.old_valid[i] = 0;
+      }
+      if (p.mode[i] == MODE_FREE && !p.old_valid[i]) {
+        eval_forces(d, i, false, false, dtp, p.Fold + 6 * i, p.Fold + 6 * i + 3);
+        p.old_valid[i] = 1;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+      double* x = p.x + 3 * i;
+      if (p.mode[i] == MODE_FREE) {
+        const double c2 = dtp * dtp / (2.0 * p.m[i]);
+        for (int a = 0; a < 3; ++a) x[a] = (x[a] + dtp * p.u[3 * i + a]) + c2 * p.Fold[6 * i + a];
+      } else if (p.mode[i] == MODE_PRESCRIBED) {
+        for (int a = 0; a < 3; ++a) x[a] = x[a] + dtp * p.u[3 * i + a];
+      }
+      for (int a = 0; a < 3; ++a) {
+        if (d.walls[a]) continue;
+        const double L = (double)n[a];
+        if (x[a] < 0.0)
+          x[a] += L;
+        else if (x[a] >= L)
+          x[a] -= L;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+      eval_forces(d, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+      const double* Fn = p.Fnew + 6 * i;
+      double* dg = p.diag + 18 * i;
+      for (int k = 0; k < 6; ++k) dg[k] = Fn[k];
+      if (p.mode[i] == MODE_FREE) {
+        const double cu = dtp / (2.0 * p.m[i]), cw = dtp / (2.0 * p.I[i]);
+        for (int a = 0; a < 3; ++a) {
+          p.u[3 * i + a] = p.u[3 * i + a] + cu * (p.Fold[6 * i + a] + Fn[a]);
+          p.w[3 * i + a] = p.w[3 * i + a] + cw * (p.Fold[6 * i + 3 + a] + Fn[3 + a]);
+          p.Fold[6 * i + a] = Fn[a];
+          p.Fold[6 * i + 3 + a] = Fn[3 + a];
+        }
+      } else if (p.mode[i] == MODE_PRESCRIBED) {
+        // Eq. (artificial_acceleration)
+        p.tpresc[i] += dtp;
+        const double ramp = 1.0 - exp(-p.presc[6 * i + 3] * p.tpresc[i] / p.presc[6 * i + 4]);
+        for (int a = 0; a < 3; ++a) {
+          p.u[3 * i + a] = p.presc[6 * i + a] * ramp;
+          p.w[3 * i + a] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // device-side health check of the particle state
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    bool ok = true;
+    for (int a = 0; a < 3; ++a)
+      ok = ok && isfinite(p.x[3 * i + a]) && isfinite(p.u[3 * i + a]) && isfinite(p.w[3 * i + a]);
+    if (!ok) atomicOr(d.status, ST_NONFINITE);
+  }
+}
+
+void launch_dem(const DevDomain& d, hipStream_t s) {
+  if (d.P <= 0) return;
+  hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
+}
+
+}  // namespace lbmdem

@@ -1,0 +1,152 @@
+// Domain initialisation, field read-out/write-in and a plain copy kernel.
+#include "internal.hpp"
+
+namespace lbmdem {
+
+// fluid at rest (deviation 0), wall layers flagged, claims cleared
+template <typename T>
+__global__ void k_init(DevDomain d) {
+  const size_t N = (size_t)d.N;
+  T* a = (T*)d.pdf[0];
+  T* b = (T*)d.pdf[1];
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % d.nx);
+    const int j = (int)((c / d.nx) % d.ny);
+    const int k = (int)(c / ((size_t)d.nx * d.ny));
+    const bool wall = (d.walls[0] && (i == 0 || i == d.nx - 1)) ||
+                      (d.walls[1] && (j == 0 || j == d.ny - 1)) ||
+                      (d.walls[2] && (k == 0 || k == d.nz - 1));
+    d.flags[c] = wall ? F_WALL : 0;
+    d.owner[c] = -1;
+    d.claim[c] = 0ull;
+    d.shellstamp[c] = 0u;
+    for (int q = 0; q < Q; ++q) {
+      a[(size_t)q * N + c] = T(0.0f);
+      b[(size_t)q * N + c] = T(0.0f);
+    }
+  }
+}
+
+template <typename T>
+__device__ inline double to_d(T v) {
+  return (double)v;
+}
+template <>
+__device__ inline double to_d<__half>(__half v) {
+  return (double)__half2float(v);
+}
+
+// which: 0 rho, 1..3 velocity component, 10+q PDF plane q (full f),
+// 40 canonical flags, 41 owner (as double)
+template <typename T>
+__global__ void k_get_plane(DevDomain d, int cur, int which, double* dst) {
+  const size_t N = (size_t)d.N;
+  const T* f = (const T*)d.pdf[cur];
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const uint8_t fl = d.flags[c];
+    const bool fluid = !(fl & (F_SOLID | F_WALL));
+    double v = 0.0;
+    if (which == 40) {
+      v = (fl & F_WALL) ? 3.0 : ((fl & F_SOLID) ? 2.0 : ((fl & F_SHELL) ? 1.0 : 0.0));
+    } else if (which == 41) {
+      v = (fl & F_SOLID) ? (double)d.owner[c] : -1.0;
+    } else if (fluid) {
+      if (which >= 10) {
+        const int q = which - 10;
+        v = to_d<T>(f[(size_t)q * N + c]) + WQ[q];
+      } else {
+        double s = 0.0;
+        for (int q = 0; q < Q; ++q) {
+          const double g = to_d<T>(f[(size_t)q * N + c]);
+          const int cq = which == 0 ? 1 : (which == 1 ? CX[q] : (which == 2 ? CY[q] : CZ[q]));
+          s += g * cq;
+        }
+        v = which == 0 ? 1.0 + s : s;
+      }
+    }
+    dst[c] = v;
+  }
+}
+
+template <typename T>
+__device__ inline T from_d(double v) {
+  return (T)v;
+}
+template <>
+__device__ inline __half from_d<__half>(double v) {
+  return __float2half_rn((float)v);
+}
+
+template <typename T>
+__global__ void k_set_plane(DevDomain d, int cur, int q, const double* src) {
+  const size_t N = (size_t)d.N;
+  T* f = (T*)d.pdf[cur];
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (size_t)gridDim.x * blockDim.x)
+    f[(size_t)q * N + c] = from_d<T>(src[c] - WQ[q]);
+}
+
+__global__ void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_copy1(uint8_t* dst, const uint8_t* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+static dim3 grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+void launch_fill_claims(const DevDomain& d, hipStream_t s) {
+  if (d.storage == 0)
+    hipLaunchKernelGGL(k_init<double>, grid_for(d.N), dim3(256), 0, s, d);
+  else if (d.storage == 1)
+    hipLaunchKernelGGL(k_init<float>, grid_for(d.N), dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_init<__half>, grid_for(d.N), dim3(256), 0, s, d);
+}
+
+void launch_fields(const DevDomain& d, int cur, int which, double* dst, hipStream_t s) {
+  if (d.storage == 0)
+    hipLaunchKernelGGL(k_get_plane<double>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+  else if (d.storage == 1)
+    hipLaunchKernelGGL(k_get_plane<float>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+  else
+    hipLaunchKernelGGL(k_get_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+}
+
+// src: one plane q (encoded in the upper bits of `cur`: cur + 2*q)
+void launch_set_pdf(const DevDomain& d, int curq, const double* src, hipStream_t s) {
+  const int cur = curq & 1, q = curq >> 1;
+  if (d.storage == 0)
+    hipLaunchKernelGGL(k_set_plane<double>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+  else if (d.storage == 1)
+    hipLaunchKernelGGL(k_set_plane<float>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+  else
+    hipLaunchKernelGGL(k_set_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+}
+
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  if (n16 > 0) {
+    size_t b = (n16 + 255) / 256;
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)b), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);
+  }
+  const size_t tail = bytes - n16 * 16;
+  if (tail)
+    hipLaunchKernelGGL(k_copy1, dim3(1), dim3(256), 0, s, (uint8_t*)dst + n16 * 16,
+                       (const uint8_t*)src + n16 * 16, tail);
+}
+
+}  // namespace lbmdem

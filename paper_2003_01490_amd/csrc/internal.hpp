@@ -1,0 +1,139 @@
+// Internal definitions shared by the kernels and the host API of lbmdem.
+//
+// Device data of one domain (all inside one caller-owned region):
+//   pdf[2]      two PDF buffers, q-major planes of N cells, storing f - w_q in
+//               the storage type (double / float / half); buffer `cur` holds
+//               the post-collision state of the current step.  Slots of solid
+//               and wall cells carry the boundary value of the link that
+//               streams out of them ("ghost" values written by the boundary
+//               kernel), so the sweep pulls all 19 directions unconditionally.
+//   flags       uint8 per cell (SOLID / WALL / SHELL bits)
+//   owner       int32 per cell, sphere id of solid cells
+//   claim       uint64 per cell, (stamp << 32 | ~id) max-claim of the mapping
+//   shellstamp  uint32 per cell, stamp of the last mapping that put the cell
+//               inside some sphere's TRT+aB shell
+//   particle SoA in FP64, per-(sphere, box-slab) force partials, contact
+//   history slots, neighbour lists and a device status word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbmdem {
+
+constexpr int Q = 19;
+constexpr uint8_t F_SOLID = 1;
+constexpr uint8_t F_WALL = 2;
+constexpr uint8_t F_SHELL = 4;
+
+constexpr int HIST_SLOTS = 24;   // contact-history slots per sphere
+constexpr int NBR_MAX = 48;      // neighbour-list capacity per sphere
+
+constexpr int MODE_FREE = 0;
+constexpr int MODE_PRESCRIBED = 1;
+constexpr int MODE_FIXED = 2;
+
+// device status bits
+constexpr int ST_NONFINITE = 1;
+constexpr int ST_HIST_FULL = 2;
+constexpr int ST_NBR_FULL = 4;
+
+// D3Q19 velocities in the order fixed by rows 2-4 of the MRT moment matrix
+// (App. A of the paper), weights 1/3, 1/18, 1/36 and opposite directions.
+static __constant__ const int CX[Q] = {0, 0, 0, -1, 1, 0, 0, -1, 1, -1, 1, 0, 0, -1, 1, 0, 0, -1, 1};
+static __constant__ const int CY[Q] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, -1, 0, 0, 1, -1, 0, 0};
+static __constant__ const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1};
+static __constant__ const int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 16, 15, 18, 17, 12, 11, 14, 13};
+static __constant__ const double WQ[Q] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                       1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+struct DevParticles {
+  double* x;      // [P][3] position
+  double* u;      // [P][3]
+  double* w;      // [P][3]
+  double* xmap;   // [P][3] position at the last mapping
+  double* R;      // [P]
+  double* rho;    // [P]
+  double* m;      // [P]
+  double* I;      // [P]
+  int* mode;      // [P]
+  double* presc;  // [P][6]: u_target[3], c_acc, t_st, release_gap
+  double* tpresc; // [P] time since the ramp started
+  double* Fprev;  // [P][6] previous un-averaged resolved F, T
+  int* prev_valid;
+  double* Ffp;    // [P][6] averaged resolved F, T of the current step
+  double* Fraw;   // [P][6]
+  double* Fold;   // [P][6] velocity-Verlet force/torque at time t
+  int* old_valid;
+  double* diag;   // [P][18] F_tot T_tot F_lub T_lub F_col T_col of the last sub-step
+  double* Fnew;   // [P][6] scratch of the current sub-step
+  int* hist_id;   // [P][HIST_SLOTS] partner code (sphere id >= 0, wall -1-face), INT_MIN free
+  double* hist_d; // [P][HIST_SLOTS][3] tangential spring
+  int* nbr;       // [P][NBR_MAX] candidate partners (ascending)
+  int* nbr_n;     // [P]
+};
+
+struct DevDomain {
+  int nx, ny, nz;
+  long long N;
+  int walls[3];
+  double wall_u_lo[3], wall_u_hi[3];
+  int storage;     // 0 f64, 1 f32, 2 f16
+  int boundary;    // 0 CLI, 1 BB
+  double s_plus, s_minus, s_bulk_shell, s_bulk_other;
+  double s_nu;     // shear rate (reconstruction)
+  double delta_ab;
+  void* pdf[2];
+  uint8_t* flags;
+  int32_t* owner;
+  unsigned long long* claim;
+  uint32_t* shellstamp;
+  DevParticles p;
+  int P;           // spheres present
+  int ZB;          // mapping blocks per sphere
+  double* partial; // [P][ZB][6]
+  int* status;
+  // DEM parameters
+  int n_sub;
+  int force_averaging;
+  double gravity[3];
+  double e_dry, poisson_ratio, friction, tc, dmin, cut_n, cut_tt, cut_tr;
+  int lub_mask;
+  double nu;
+  double skin;     // neighbour-list skin
+};
+
+__host__ __device__ inline long long cidx(const DevDomain& d, int i, int j, int k) {
+  return (long long)i + (long long)d.nx * ((long long)j + (long long)d.ny * (long long)k);
+}
+
+__device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// full modulo for indices that may lie more than one period away
+__device__ inline int wrapmod(int i, int n) {
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// minimum image of a distance component on periodic axes
+__device__ inline double min_image(double v, int n, int wall) {
+  if (wall) return v;
+  double L = (double)n;
+  if (v > 0.5 * L) return v - L;
+  if (v < -0.5 * L) return v + L;
+  return v;
+}
+
+// host-side launchers (implemented in the .hip files)
+void launch_sweep(const DevDomain& d, int cur, hipStream_t s);
+void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
+                    hipStream_t s);
+void launch_dem(const DevDomain& d, hipStream_t s);
+void launch_fields(const DevDomain& d, int cur, int field, double* dst, hipStream_t s);
+void launch_set_pdf(const DevDomain& d, int cur, const double* src, hipStream_t s);
+void launch_fill_claims(const DevDomain& d, hipStream_t s);
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace lbmdem

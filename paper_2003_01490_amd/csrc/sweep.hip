@@ -1,0 +1,191 @@
+// Fused D3Q19 pull stream + TRT+aB collide (Eqs. LBM_Stream, LBM_Collide, MRT
+// with the rates of Eqs. TRTmatrix / TRTbulkmatrix, adaptive shell of Sec. 2.3.2).
+//
+// One thread per cell, one block per whole x-row group, so that the +-1
+// x-shifted loads of a row stay inside the block and every source value is
+// fetched from HBM once.  Solid and wall cells exit at once; their PDF slots
+// carry the boundary values of the links that stream out of them (written by
+// the boundary kernel), so every fluid cell pulls 19 values without branching.
+//
+// Collision in deviation variables g = f - w_q:
+//   TRT in velocity space: g~_q = g_q - s+ (g+_q - e+_q) - s- (g-_q - e-_q),
+//   which equals M^-1 S_TRT (m^eq - M f) because the moment rows of App. A are
+//   each even or odd under q -> q-bar; plus, for rows 5 and 6 of M (kinetic
+//   energy and its square), the rank-2 correction
+//   w_q (s_b - s+) [M_4q (m4eq - m4)/N_4 + M_5q (m5eq - m5)/N_5]
+//   with N_4 = 2/3, N_5 = 2 (M^-1 = W M^T diag(1/N)).  s_b is the TRT+B rate
+//   in shell cells (TRT+aB), everywhere (TRT+B), or s+ (TRT, SRT).
+#include "internal.hpp"
+
+namespace lbmdem {
+
+template <typename T>
+struct Store;
+
+template <>
+struct Store<double> {
+  using C = double;
+  __device__ static inline double load(const double* p) { return *p; }
+  __device__ static inline void store(double* p, double v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Store<float> {
+  using C = float;
+  __device__ static inline float load(const float* p) { return *p; }
+  __device__ static inline void store(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Store<__half> {
+  using C = float;
+  __device__ static inline float load(const __half* p) { return __half2float(*p); }
+  __device__ static inline void store(__half* p, float v) {
+    __half h = __float2half_rn(v);
+    __builtin_nontemporal_store(*reinterpret_cast<unsigned short*>(&h),
+                                reinterpret_cast<unsigned short*>(p));
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ src, T* __restrict__ dst,
+                                               const uint8_t* __restrict__ flags, int nx, int ny,
+                                               int nz, unsigned int N,
+                                               typename Store<T>::C sp,
+                                               typename Store<T>::C sm,
+                                               typename Store<T>::C db_shell,
+                                               typename Store<T>::C db_other) {
+  using C = typename Store<T>::C;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const unsigned int nxy = (unsigned int)nx * (unsigned int)ny;
+  const unsigned int idx = (unsigned int)x + (unsigned int)nx * (unsigned int)y + nxy * (unsigned int)z;
+  const uint8_t fl = flags[idx];
+  if (fl & (F_SOLID | F_WALL)) return;
+
+  // source of direction q is x - c_q: index [1 - c] of these triples
+  const unsigned int X0 = (unsigned int)(x == 0 ? nx - 1 : x - 1), X1 = (unsigned int)x,
+                     X2 = (unsigned int)(x == nx - 1 ? 0 : x + 1);
+  const unsigned int Y0 = (unsigned int)(y == 0 ? ny - 1 : y - 1) * (unsigned int)nx,
+                     Y1 = (unsigned int)y * (unsigned int)nx,
+                     Y2 = (unsigned int)(y == ny - 1 ? 0 : y + 1) * (unsigned int)nx;
+  const unsigned int Z0 = (unsigned int)(z == 0 ? nz - 1 : z - 1) * nxy, Z1 = (unsigned int)z * nxy,
+                     Z2 = (unsigned int)(z == nz - 1 ? 0 : z + 1) * nxy;
+
+  const size_t NN = (size_t)N;
+#define LD(q, xs, ys, zs) Store<T>::load(src + (size_t)(q) * NN + (xs + ys + zs))
+  C g[Q];
+  g[0] = LD(0, X1, Y1, Z1);
+  g[1] = LD(1, X1, Y0, Z1);    // c = ( 0, 1, 0)
+  g[2] = LD(2, X1, Y2, Z1);    // c = ( 0,-1, 0)
+  g[3] = LD(3, X2, Y1, Z1);    // c = (-1, 0, 0)
+  g[4] = LD(4, X0, Y1, Z1);    // c = ( 1, 0, 0)
+  g[5] = LD(5, X1, Y1, Z0);    // c = ( 0, 0, 1)
+  g[6] = LD(6, X1, Y1, Z2);    // c = ( 0, 0,-1)
+  g[7] = LD(7, X2, Y0, Z1);    // c = (-1, 1, 0)
+  g[8] = LD(8, X0, Y0, Z1);    // c = ( 1, 1, 0)
+  g[9] = LD(9, X2, Y2, Z1);    // c = (-1,-1, 0)
+  g[10] = LD(10, X0, Y2, Z1);  // c = ( 1,-1, 0)
+  g[11] = LD(11, X1, Y0, Z0);  // c = ( 0, 1, 1)
+  g[12] = LD(12, X1, Y2, Z0);  // c = ( 0,-1, 1)
+  g[13] = LD(13, X2, Y1, Z0);  // c = (-1, 0, 1)
+  g[14] = LD(14, X0, Y1, Z0);  // c = ( 1, 0, 1)
+  g[15] = LD(15, X1, Y0, Z2);  // c = ( 0, 1,-1)
+  g[16] = LD(16, X1, Y2, Z2);  // c = ( 0,-1,-1)
+  g[17] = LD(17, X2, Y1, Z2);  // c = (-1, 0,-1)
+  g[18] = LD(18, X0, Y1, Z2);  // c = ( 1, 0,-1)
+#undef LD
+
+  // moments (rho0 = 1: u = j; deviations carry no mass or momentum of w_q)
+  const C sumd = ((g[7] + g[8]) + (g[9] + g[10])) + ((g[11] + g[12]) + (g[13] + g[14])) +
+                 ((g[15] + g[16]) + (g[17] + g[18]));
+  const C suma = ((g[1] + g[2]) + (g[3] + g[4])) + (g[5] + g[6]);
+  const C rho = (g[0] + suma) + sumd;  // rho - 1
+  const C ux = ((g[4] - g[3]) + (g[8] - g[7])) + ((g[10] - g[9]) + (g[14] - g[13])) + (g[18] - g[17]);
+  const C uy = ((g[1] - g[2]) + (g[7] + g[8])) - ((g[9] + g[10]) - (g[11] - g[12])) + (g[15] - g[16]);
+  const C uz = ((g[5] - g[6]) + (g[11] + g[12])) + ((g[13] + g[14]) - (g[15] + g[16])) - (g[17] + g[18]);
+  const C usq = ux * ux + uy * uy + uz * uz;
+
+  // bulk correction amplitudes (rows 4 and 5 of M, 0-based)
+  const C db = (fl & F_SHELL) ? db_shell : db_other;  // s_b - s+
+  const C m4 = sumd - g[0];
+  const C m5 = (g[0] - C(2) * suma) + sumd;
+  const C A4 = db * (C(1.5) * (usq - m4));
+  const C A5 = db * (C(-0.5) * m5);
+
+  const C w0 = C(1.0 / 3.0), w1 = C(1.0 / 18.0), w2 = C(1.0 / 36.0);
+  C o[Q];
+  {
+    const C e0 = w0 * (rho - C(1.5) * usq);
+    o[0] = (g[0] - sp * (g[0] - e0)) + w0 * (A5 - A4);
+  }
+  const C ba = C(-2) * w1 * A5;
+  const C bd = w2 * (A4 + A5);
+  const C base1 = w1 * (rho - C(1.5) * usq);
+  const C base2 = w2 * (rho - C(1.5) * usq);
+#define PAIR(a, b, w, base, cu, bulk)                 \
+  {                                                   \
+    const C cu_ = (cu);                               \
+    const C ep = (base) + C(4.5) * (w) * cu_ * cu_;   \
+    const C em = C(3) * (w) * cu_;                    \
+    const C gp = C(0.5) * (g[a] + g[b]);              \
+    const C gm = C(0.5) * (g[a] - g[b]);              \
+    const C dp = sp * (gp - ep);                      \
+    const C dm = sm * (gm - em);                      \
+    o[a] = ((g[a] - dp) - dm) + (bulk);               \
+    o[b] = ((g[b] - dp) + dm) + (bulk);               \
+  }
+  PAIR(1, 2, w1, base1, uy, ba)
+  PAIR(4, 3, w1, base1, ux, ba)
+  PAIR(5, 6, w1, base1, uz, ba)
+  PAIR(7, 10, w2, base2, uy - ux, bd)
+  PAIR(8, 9, w2, base2, ux + uy, bd)
+  PAIR(11, 16, w2, base2, uy + uz, bd)
+  PAIR(12, 15, w2, base2, uz - uy, bd)
+  PAIR(13, 18, w2, base2, uz - ux, bd)
+  PAIR(14, 17, w2, base2, ux + uz, bd)
+#undef PAIR
+
+#pragma unroll
+  for (int q = 0; q < Q; ++q) Store<T>::store(dst + (size_t)q * NN + idx, o[q]);
+}
+
+template <typename T>
+static void launch_sweep_t(const DevDomain& d, int cur, hipStream_t s) {
+  dim3 block, grid;
+  if (d.nx <= 256) {
+    // whole rows per block: the periodic x-wrap stays inside the block
+    block.x = d.nx;
+    block.y = 256 / d.nx;
+  } else {
+    const int cand[4] = {256, 192, 128, 64};
+    block.x = 256;
+    for (int c : cand)
+      if (d.nx % c == 0) {
+        block.x = c;
+        break;
+      }
+    block.y = 256 / block.x;
+  }
+  block.z = 1;
+  grid.x = (d.nx + block.x - 1) / block.x;
+  grid.y = (d.ny + block.y - 1) / block.y;
+  grid.z = d.nz;
+  using C = typename Store<T>::C;
+  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, (const T*)d.pdf[cur], (T*)d.pdf[1 - cur],
+                     (const uint8_t*)d.flags, d.nx, d.ny, d.nz, (unsigned int)d.N, (C)d.s_plus,
+                     (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
+}
+
+void launch_sweep(const DevDomain& d, int cur, hipStream_t s) {
+  if (d.storage == 0)
+    launch_sweep_t<double>(d, cur, s);
+  else if (d.storage == 1)
+    launch_sweep_t<float>(d, cur, s);
+  else
+    launch_sweep_t<__half>(d, cur, s);
+}
+
+}  // namespace lbmdem

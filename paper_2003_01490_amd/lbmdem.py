@@ -1,0 +1,282 @@
+"""Python binding of the lbmdem C-ABI (``include/lbmdem.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``liblbmdem.so``.  PyTorch provides the device region (a uint8 tensor the
+domain lives in) and the stream.  There is no fallback: if the library is
+missing this module raises at import of ``lib()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "liblbmdem.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lbmdem.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERLAP, EUNSTABLE, ECAPACITY, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+TRT_AB, TRT_B, TRT, SRT = 0, 1, 2, 3
+BC_CLI, BC_BOUNCE_BACK = 0, 1
+STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
+FREE, PRESCRIBED, FIXED = 0, 1, 2
+FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_FLAGS, FIELD_OWNER = 0, 1, 2, 3, 4
+SPHERE_STATE = 42
+
+
+class LbmdemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbmdem error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("walls", C.c_int32 * 3),
+        ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
+        ("nu", C.c_double), ("magic_lambda", C.c_double), ("lambda_b", C.c_double),
+        ("delta_ab", C.c_double),
+        ("collision", C.c_int32), ("boundary", C.c_int32), ("storage", C.c_int32),
+        ("n_sub", C.c_int32), ("force_averaging", C.c_int32),
+        ("gravity", C.c_double * 3),
+        ("e_dry", C.c_double), ("poisson_ratio", C.c_double), ("friction", C.c_double),
+        ("tc", C.c_double), ("dmin", C.c_double),
+        ("cut_n", C.c_double), ("cut_tt", C.c_double), ("cut_tr", C.c_double),
+        ("lub_mask", C.c_int32), ("max_spheres", C.c_int32),
+        ("max_radius", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``liblbmdem.so`` (built by ``paper_2003_01490_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # PyTorch ships its own HIP runtime under the same soname; importing it
+    # first makes this library bind to that runtime, so device pointers and
+    # streams from torch are valid here.
+    import torch  # noqa: F401
+
+    if not os.path.exists(SO_PATH):
+        raise ImportError(f"{SO_PATH} is not built; run `python -m paper_2003_01490_amd.build`")
+    L = C.CDLL(SO_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    sig = {
+        "lbmdem_config_init": (C.c_int32, [C.POINTER(Config)]),
+        "lbmdem_footprint_bytes": (C.c_size_t, [C.POINTER(Config)]),
+        "lbmdem_create": (C.c_int32, [C.POINTER(Config), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "lbmdem_destroy": (C.c_int32, [vp]),
+        "lbmdem_add_spheres": (C.c_int32, [vp, C.c_int32, dp, dp, dp, dp, dp, ip]),
+        "lbmdem_update_spheres": (C.c_int32, [vp, C.c_int32, ip, dp, dp, dp, C.c_int32]),
+        "lbmdem_set_sphere_mode": (C.c_int32, [vp, C.c_int32, C.c_int32, dp, C.c_double,
+                                               C.c_double, C.c_double]),
+        "lbmdem_step": (C.c_int32, [vp, C.c_int32]),
+        "lbmdem_sync": (C.c_int32, [vp]),
+        "lbmdem_num_spheres": (C.c_int32, [vp]),
+        "lbmdem_get_sphere_state": (C.c_int32, [vp, C.c_int32, dp]),
+        "lbmdem_get_field": (C.c_int32, [vp, C.c_int32, vp, C.c_size_t, C.c_int32]),
+        "lbmdem_set_pdf": (C.c_int32, [vp, dp]),
+        "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
+        "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
+        "lbmdem_sweep_bytes": (C.c_double, [vp]),
+        "lbmdem_device_copy": (C.c_int32, [vp, vp, C.c_size_t, vp]),
+        "lbmdem_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions ``include/lbmdem.h`` declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lbmdem_[a-z0-9_]+)\s*\(", text)))
+
+
+def default_config(**kw) -> Config:
+    c = Config()
+    lib().lbmdem_config_init(C.byref(c))
+    for k, v in kw.items():
+        if isinstance(v, (tuple, list, np.ndarray)):
+            arr = getattr(c, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def footprint_bytes(cfg: Config) -> int:
+    return int(lib().lbmdem_footprint_bytes(C.byref(cfg)))
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _arr(v, n):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(n))
+
+
+class Domain:
+    """One simulation domain resident on a GPU.
+
+    The device region is a torch uint8 tensor owned by this object; all work
+    runs on ``stream`` (default: torch's current stream of ``device``)."""
+
+    def __init__(self, cfg: Config, device="cuda:0", stream=None, region=None):
+        import torch
+
+        self.cfg = cfg
+        self.n = (cfg.nx, cfg.ny, cfg.nz)
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self.nbytes = footprint_bytes(cfg)
+        if self.nbytes == 0:
+            raise LbmdemError(EINVAL, "invalid configuration")
+        if region is None:
+            region = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        self.region = region
+        base = region.data_ptr()
+        ptr = (base + 255) & ~255
+        if ptr + self.nbytes > base + region.numel():
+            raise LbmdemError(ENOMEM, "region too small")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(region.device)
+        h = C.c_void_p()
+        rc = lib().lbmdem_create(C.byref(cfg), C.c_void_p(ptr), self.nbytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise LbmdemError(rc, lib().lbmdem_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmdemError(rc, lib().lbmdem_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbmdem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- spheres ----------------------------------------------------------
+    def add_spheres(self, x, R, rho, u=None, w=None):
+        x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+        n = x.shape[0]
+        x = _arr(x, 3 * n)
+        u = _arr(np.zeros((n, 3)) if u is None else u, 3 * n)
+        w = _arr(np.zeros((n, 3)) if w is None else w, 3 * n)
+        R = _arr(np.broadcast_to(np.asarray(R, dtype=np.float64), (n,)), n)
+        rho = _arr(np.broadcast_to(np.asarray(rho, dtype=np.float64), (n,)), n)
+        ids = np.zeros(n, dtype=np.int32)
+        self._check(lib().lbmdem_add_spheres(self.h, n, _dp(x), _dp(u), _dp(w), _dp(R), _dp(rho),
+                                             ids.ctypes.data_as(C.POINTER(C.c_int32))))
+        return ids
+
+    def try_add_spheres(self, x, R, rho, u=None, w=None) -> int:
+        try:
+            self.add_spheres(x, R, rho, u, w)
+            return OK
+        except LbmdemError as e:
+            return e.code
+
+    def update_spheres(self, ids, x=None, u=None, w=None):
+        ids = np.ascontiguousarray(np.atleast_1d(ids), dtype=np.int32)
+        n = len(ids)
+        mask = (1 if x is not None else 0) | (2 if u is not None else 0) | (4 if w is not None else 0)
+        z = np.zeros(3 * n)
+        xa = _arr(x, 3 * n) if x is not None else z
+        ua = _arr(u, 3 * n) if u is not None else z
+        wa = _arr(w, 3 * n) if w is not None else z
+        self._check(lib().lbmdem_update_spheres(self.h, n, ids.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                _dp(xa), _dp(ua), _dp(wa), mask))
+
+    def set_mode(self, sid, mode, u_target=(0, 0, 0), c_acc=10.0, t_st=1.0, release_gap=0.0):
+        ut = _arr(u_target, 3)
+        self._check(lib().lbmdem_set_sphere_mode(self.h, int(sid), int(mode), _dp(ut), float(c_acc),
+                                                 float(t_st), float(release_gap)))
+
+    def num_spheres(self) -> int:
+        return int(lib().lbmdem_num_spheres(self.h))
+
+    def sphere(self, sid) -> dict:
+        out = np.zeros(SPHERE_STATE)
+        self._check(lib().lbmdem_get_sphere_state(self.h, int(sid), _dp(out)))
+        return dict(x=out[0:3].copy(), u=out[3:6].copy(), w=out[6:9].copy(),
+                    F_fp=out[9:12].copy(), T_fp=out[12:15].copy(),
+                    F_tot=out[15:18].copy(), T_tot=out[18:21].copy(),
+                    F_lub=out[21:24].copy(), T_lub=out[24:27].copy(),
+                    F_col=out[27:30].copy(), T_col=out[30:33].copy(),
+                    mode=int(out[33]), R=out[34], rho=out[35],
+                    F_raw=out[36:39].copy(), T_raw=out[39:42].copy())
+
+    # --- time stepping ----------------------------------------------------
+    def step(self, n=1):
+        self._check(lib().lbmdem_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().lbmdem_sync(self.h))
+
+    # --- fields -------------------------------------------------------------
+    def field(self, which: str) -> np.ndarray:
+        nx, ny, nz = self.n
+        if which == "rho":
+            out = np.zeros(self.N)
+            shape, fid = (nz, ny, nx), FIELD_RHO
+        elif which == "vel":
+            out = np.zeros(3 * self.N)
+            shape, fid = (3, nz, ny, nx), FIELD_VEL
+        elif which == "pdf":
+            out = np.zeros(19 * self.N)
+            shape, fid = (19, nz, ny, nx), FIELD_PDF
+        elif which == "flags":
+            out = np.zeros(self.N, dtype=np.uint8)
+            shape, fid = (nz, ny, nx), FIELD_FLAGS
+        elif which == "owner":
+            out = np.zeros(self.N, dtype=np.int32)
+            shape, fid = (nz, ny, nx), FIELD_OWNER
+        else:
+            raise ValueError(which)
+        self._check(lib().lbmdem_get_field(self.h, fid, C.c_void_p(out.ctypes.data), out.nbytes, 0))
+        return out.reshape(shape)
+
+    def flags(self):
+        return self.field("flags"), self.field("owner")
+
+    def set_pdf(self, f):
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(19 * self.N))
+        self._check(lib().lbmdem_set_pdf(self.h, _dp(f)))
+
+    # --- profiling --------------------------------------------------------
+    def set_profiling(self, on: bool):
+        self._check(lib().lbmdem_set_profiling(self.h, int(bool(on))))
+
+    def profile(self, kernel: int):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._check(lib().lbmdem_get_profile(self.h, int(kernel), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+    def sweep_bytes(self) -> float:
+        return float(lib().lbmdem_sweep_bytes(self.h))
+
+
+def device_copy(dst_tensor, src_tensor, nbytes, stream):
+    rc = lib().lbmdem_device_copy(C.c_void_p(dst_tensor.data_ptr()), C.c_void_p(src_tensor.data_ptr()),
+                                  int(nbytes), C.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise LbmdemError(rc, "device copy failed")

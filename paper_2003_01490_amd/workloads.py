@@ -1,0 +1,156 @@
+"""Seeded synthetic workloads (inputs only, none of the method's arithmetic).
+
+Both the GPU path and the test oracle take their inputs from here: lattice
+size, fluid and DEM parameters, and sphere positions/velocities drawn with
+``numpy.random.default_rng(seed)``.  The paper's experiments use physical
+tables (Sec. 4.4, Table sphereWallCollision); the values below convert them to
+lattice units where a workload asks for it.
+
+Workloads:
+  settling_32     - 32^3, z walls, nu 0.01, D 8, density ratio 2.5, centre
+                    (16,16,20) + U[-1/2,1/2]^3, gravity 1e-5, 300 steps, FP64.
+  contact_32      - the same domain with the sphere 0.7 above the bottom wall
+                    and u_z = -0.01 (contact and lubrication within 300 steps).
+  sphere_wall     - 128x128x256, z walls, D 20, Stokes number 100 from a seeded
+                    density ratio U[2,8] and viscosity logU[0.005,0.05]
+                    (rejecting u_s > 0.1), released from the ramp of
+                    Eq. (artificial_acceleration) one diameter above the wall.
+  dense           - cubic lattice with z walls, equal spheres placed by seeded
+                    random sequential addition with a surface gap >= 1 to
+                    every other sphere and wall.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Table sphereWallCollision (Sec. 4.4.2), St = 100 row: fluid density, dynamic
+# viscosity, diameter, particle density, gravity (SI)
+_ST100 = dict(rho_f=953.0, mu_f=0.02, D=0.004, rho_p=7800.0, g=9.81)
+
+
+@dataclass
+class Workload:
+    name: str
+    params: dict
+    x: np.ndarray
+    R: np.ndarray
+    rho: np.ndarray
+    u: np.ndarray
+    w: np.ndarray
+    steps: int
+    ramp: dict | None = None     # prescribed-velocity protocol of sphere 0
+    meta: dict = field(default_factory=dict)
+
+
+def base_params(**kw) -> dict:
+    """Defaults of the paper: Lambda 3/16, Lambda_b 100, delta_aB 2, cut-offs
+    2/3, 1/2, 1/2, n_sub 10, T_c and delta_min by its relations; e_dry 0.97
+    (Table sphereWallCollision), nu_p 0.23 and mu_p 0.15 (TW1 of Table
+    obliqueCollision)."""
+    p = dict(nx=32, ny=32, nz=32, walls=(0, 0, 1), wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
+             nu=0.01, magic_lambda=3.0 / 16.0, lambda_b=100.0, delta_ab=2.0, collision=0,
+             boundary=0, n_sub=10, force_averaging=1, gravity=(0.0, 0.0, 0.0), e_dry=0.97,
+             poisson_ratio=0.23, friction=0.15, tc=-1.0, dmin=-1.0, cut_n=2.0 / 3.0, cut_tt=0.5,
+             cut_tr=0.5, lub_mask=7, max_spheres=1)
+    p.update(kw)
+    return p
+
+
+def settling_32(seed: int = 0) -> Workload:
+    rng = np.random.default_rng(seed)
+    x = np.array([16.0, 16.0, 20.0]) + rng.uniform(-0.5, 0.5, 3)
+    p = base_params(nu=0.01, gravity=(0.0, 0.0, -1e-5), max_spheres=1)
+    return Workload("settling_32", p, x[None], np.array([4.0]), np.array([2.5]), np.zeros((1, 3)),
+                    np.zeros((1, 3)), 300, meta=dict(seed=seed))
+
+
+def contact_32(seed: int = 0) -> Workload:
+    rng = np.random.default_rng(seed)
+    x = np.array([16.0, 16.0, 1.0 + 4.0 + 0.7])
+    x[:2] += rng.uniform(-0.5, 0.5, 2)
+    p = base_params(nu=0.01, gravity=(0.0, 0.0, -1e-5), max_spheres=1)
+    return Workload("contact_32", p, x[None], np.array([4.0]), np.array([2.5]),
+                    np.array([[0.0, 0.0, -0.01]]), np.zeros((1, 3)), 300, meta=dict(seed=seed))
+
+
+def sphere_wall(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 256, D: float = 20.0,
+                St: float = 100.0, default_draw: bool = True) -> Workload:
+    """Sphere-wall collision at a given Stokes number (Sec. 4.4).  With
+    ``default_draw`` the density ratio and viscosity of the paper's St = 100
+    row are used (rho_p/rho_f = 7800/953, nu from the lattice speed u_s);
+    otherwise they are drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    if default_draw:
+        rho_r = _ST100["rho_p"] / _ST100["rho_f"]
+        u_s = 0.028
+        nu = u_s * D * rho_r / (9.0 * St)
+    else:
+        while True:
+            rho_r = rng.uniform(2.0, 8.0)
+            nu = math.exp(rng.uniform(math.log(0.005), math.log(0.05)))
+            u_s = 9.0 * St * nu / (rho_r * D)
+            if u_s <= 0.1:
+                break
+    # gravity from the Froude number g D / u_s^2 of the St = 100 experiment
+    nu_phys = _ST100["mu_f"] / _ST100["rho_f"]
+    us_phys = 9.0 * St * nu_phys * _ST100["rho_f"] / (_ST100["rho_p"] * _ST100["D"])
+    fr = _ST100["g"] * _ST100["D"] / us_phys ** 2
+    g = fr * u_s ** 2 / D
+    x = np.array([nx / 2.0, ny / 2.0, (nz - 1.0) - 1.5 * D])
+    x[:2] += rng.uniform(-0.5, 0.5, 2)
+    p = base_params(nx=nx, ny=ny, nz=nz, nu=nu, gravity=(0.0, 0.0, -g), max_spheres=1)
+    t_st = rho_r * D * D / (18.0 * nu)
+    ramp = dict(u_target=(0.0, 0.0, -u_s), c_acc=10.0, t_st=t_st, release_gap=D)
+    return Workload("sphere_wall", p, x[None], np.array([D / 2]), np.array([rho_r]),
+                    np.zeros((1, 3)), np.zeros((1, 3)), 20000, ramp=ramp,
+                    meta=dict(seed=seed, St=St, u_s=u_s, rho_r=rho_r, nu=nu, g=g, froude=fr))
+
+
+def dense(seed: int = 0, n: int = 96, count: int = 156, D: float = 12.0, rho_r: float = 2.0,
+          nu: float = 0.02, g: float = 2e-6, min_gap: float = 1.0, steps: int = 100,
+          nxyz: tuple | None = None) -> Workload:
+    """Random sequential addition of equal spheres (periodic x, y; z walls)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = nxyz if nxyz else (n, n, n)
+    R = D / 2.0
+    cell = D + min_gap
+    gx, gy, gz = int(nx // cell) or 1, int(ny // cell) or 1, int(nz // cell) or 1
+    grid: dict = {}
+    pts = []
+    tries = 0
+    lo_z, hi_z = 1.0 + R + min_gap, (nz - 1.0) - R - min_gap
+    while len(pts) < count:
+        tries += 1
+        if tries > 200 * count + 100000:
+            raise RuntimeError("could not place the requested number of spheres")
+        c = np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(lo_z, hi_z)])
+        key = (int(c[0] / nx * gx) % gx, int(c[1] / ny * gy) % gy, min(int(c[2] / nz * gz), gz - 1))
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    kk = ((key[0] + dx) % gx, (key[1] + dy) % gy, key[2] + dz)
+                    for j in grid.get(kk, ()):
+                        d = c - pts[j]
+                        d[0] -= nx * round(d[0] / nx)
+                        d[1] -= ny * round(d[1] / ny)
+                        if np.linalg.norm(d) < D + min_gap:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            grid.setdefault(key, []).append(len(pts))
+            pts.append(c)
+    x = np.array(pts)
+    p = base_params(nx=nx, ny=ny, nz=nz, nu=nu, gravity=(0.0, 0.0, -g), max_spheres=count)
+    frac = count * (4.0 / 3.0) * math.pi * R ** 3 / (nx * ny * nz)
+    return Workload("dense", p, x, np.full(count, R), np.full(count, rho_r), np.zeros((count, 3)),
+                    np.zeros((count, 3)), steps, meta=dict(seed=seed, solid_fraction=frac))

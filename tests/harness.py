@@ -1,0 +1,94 @@
+"""Builds matching oracle and GPU domains from one seeded workload and compares
+them.  The oracle is only called here (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+from paper_2003_01490_amd import workloads as W
+
+ORACLE_KEYS = set(O.RefConfig._fields_ and [f[0] for f in O.RefConfig._fields_])
+
+
+def oracle_domain(wl: W.Workload, **over):
+    p = dict(wl.params)
+    p.update(over)
+    p = {k: v for k, v in p.items() if k in ORACLE_KEYS}
+    d = O.RefDomain(O.make_config(**p))
+    for i in range(len(wl.R)):
+        d.add_sphere(wl.x[i], wl.R[i], wl.rho[i], u=wl.u[i], w=wl.w[i])
+    if wl.ramp is not None:
+        r = wl.ramp
+        d.set_mode(0, O.MODE_PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
+    return d
+
+
+def gpu_domain(wl: W.Workload, storage=0, device="cuda:0", **over):
+    from paper_2003_01490_amd import lbmdem as L
+
+    p = dict(wl.params)
+    p.update(over)
+    gkeys = {f[0] for f in L.Config._fields_}
+    p = {k: v for k, v in p.items() if k in gkeys}
+    p["storage"] = storage
+    p["max_radius"] = float(max(wl.R)) if len(wl.R) else 1.0
+    p["max_spheres"] = max(p.get("max_spheres", 1), len(wl.R), 1)
+    d = L.Domain(L.default_config(**p), device=device)
+    if len(wl.R):
+        d.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
+    if wl.ramp is not None:
+        r = wl.ramp
+        d.set_mode(0, L.PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
+    return d
+
+
+def rel_field_err(a, b):
+    scale = max(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)
+
+
+def sphere_errs(sa: dict, sb: dict, D: float, scale: dict | None = None):
+    """Errors of one sphere's state against the reference sb.  Positions are
+    relative to the diameter D; velocities, angular velocities, forces and
+    torques relative to the magnitudes in ``scale`` (keys u, F; defaults to
+    the reference's own magnitudes).  Angular velocities are scaled by u/R and
+    torques by F R, since a sphere that barely rotates has w at rounding level."""
+    R = D / 2
+    us = max((scale or {}).get("u", 0.0), np.abs(sb["u"]).max(), 1e-300)
+    Fs = max((scale or {}).get("F", 0.0), np.abs(sb["F_tot"]).max(), 1e-300)
+    out = {"x": float(np.abs(sa["x"] - sb["x"]).max() / D)}
+    out["u"] = float(np.abs(sa["u"] - sb["u"]).max() / us)
+    out["w"] = float(np.abs(sa["w"] - sb["w"]).max() * R / us)
+    for k in ("F_fp", "F_raw", "F_tot", "F_lub", "F_col"):
+        out[k] = float(np.abs(sa[k] - sb[k]).max() / Fs)
+    for k in ("T_fp", "T_raw"):
+        out[k] = float(np.abs(sa[k] - sb[k]).max() / (Fs * R))
+    return out
+
+
+class Scales:
+    """Running maxima of the reference trajectory (velocity and force)."""
+
+    def __init__(self, weight=0.0):
+        self.u = 0.0
+        self.F = weight
+
+    def update(self, s):
+        self.u = max(self.u, float(np.abs(s["u"]).max()))
+        self.F = max(self.F, float(np.abs(s["F_tot"]).max()), float(np.abs(s["F_fp"]).max()))
+        return {"u": self.u, "F": self.F}
+
+
+def weight(wl, i=0):
+    """Buoyant weight V (rho_p - 1) |g| of sphere i (force scale)."""
+    g = np.linalg.norm(np.asarray(wl.params.get("gravity", (0, 0, 0)), dtype=float))
+    return 4.0 / 3.0 * np.pi * wl.R[i] ** 3 * abs(wl.rho[i] - 1.0) * g
+
+
+def random_pdf(n, seed, amp=0.02, u0=(0.0, 0.0, 0.0)):
+    """Equilibrium at rho 1 and u0 plus seeded noise (input generator)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    feq = O.equilibrium(1.0, np.asarray(u0, dtype=float))
+    f = feq[:, None, None, None] * (1.0 + amp * rng.standard_normal((19, nz, ny, nx)))
+    return f

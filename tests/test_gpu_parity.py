@@ -1,0 +1,319 @@
+"""GPU (HIP library through the C-ABI) against the FP64 oracle.
+
+FP64 storage: f, rho and u within 1e-12 of max|f| (u is a sum of f c_q with
+cancellation, so its error is bounded in units of f; it is also held to 1e-9
+of max|u| against gross errors), positions within 1e-12 D, sphere velocities
+and forces within 1e-10 of the trajectory's largest |u| and |F|; cell flags
+and owners bit for bit.  Reduced storage (FP32, FP16 deviations from w_q): errors against the
+oracle are printed and held to the bounds stated in each test.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_01490_amd import workloads as W
+
+from harness import Scales, gpu_domain, oracle_domain, random_pdf, sphere_errs, weight
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _compare_fields(g, o, tol=TOL):
+    cg, og = g.flags()
+    co, oo = o.flags()
+    assert np.array_equal(cg, co), "flags differ"
+    sol = co == O.SOLID
+    assert np.array_equal(og[sol], oo[sol]), "owners differ"
+    fg, fo = g.field("pdf"), o.field("pdf")
+    fs = np.abs(fo).max()
+    fl = co <= O.SHELL
+    rg, ro = g.field("rho"), o.field("rho")
+    ug, uo = g.field("vel"), o.field("vel")
+    errs = {
+        "pdf": float(np.abs(fg - fo).max() / fs),
+        "rho": float(np.abs(rg[fl] - ro[fl]).max() / fs),
+        "vel": float(np.abs(ug - uo).max() / fs),
+    }
+    rel_u = float(np.abs(ug - uo).max() / max(np.abs(uo).max(), 1e-300))
+    print("  field errors", errs, f"u rel {rel_u:.1e}", flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    assert rel_u <= 1e-9 or np.abs(uo).max() == 0.0
+
+
+@pytest.mark.parametrize("coll", [O.TRT_AB, O.TRT_B, O.TRT, O.SRT])
+def test_fluid_only_periodic_random_pdf(coll):
+    n = (17, 12, 9)  # ragged x, several blocks in y and z
+    _case(f"fluid periodic {n} collision {coll}")
+    wl = W.Workload("fluid", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 0), nu=0.03,
+                                           collision=coll, max_spheres=1),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    f = random_pdf(n, seed=coll, u0=(0.02, -0.01, 0.015))
+    o = oracle_domain(wl)
+    g = gpu_domain(wl)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(25)
+    g.step(25)
+    _compare_fields(g, o)
+
+
+def test_couette_channel_and_moving_walls():
+    n = (8, 6, 14)
+    _case(f"couette {n}")
+    wl = W.Workload("couette", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.1,
+                                             wall_u_hi=(0.02, 0.005, 0.0),
+                                             wall_u_lo=(-0.01, 0.0, 0.0), max_spheres=1),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    f = random_pdf(n, seed=11)
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(60)
+    g.step(60)
+    _compare_fields(g, o)
+
+
+def test_walls_on_all_axes():
+    n = (12, 11, 10)
+    _case(f"closed box {n}")
+    wl = W.Workload("box", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(1, 1, 1), nu=0.05,
+                                         max_spheres=2),
+                    np.array([[4.3, 5.1, 4.9], [8.0, 5.5, 5.2]]), np.array([1.9, 1.7]),
+                    np.array([2.0, 3.0]), np.array([[0.01, 0.0, -0.005], [-0.01, 0.002, 0.0]]),
+                    np.zeros((2, 3)), 40)
+    f = random_pdf(n, seed=12)
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(wl.steps)
+    g.step(wl.steps)
+    _compare_fields(g, o)
+    for i in range(2):
+        e = sphere_errs(g.sphere(i), o.sphere(i), 2 * wl.R[i])
+        print("  sphere", i, {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        assert max(e.values()) < 1e-10
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_mapping_bit_exact(storage):
+    n = (30, 28, 26)
+    _case(f"mapping {n} storage {storage}")
+    rng = np.random.default_rng(5)
+    xs, Rs = [], []
+    # dyadic centres so that cell centres fall exactly on some surfaces
+    cand = [([7.0, 7.5, 8.0], 2.5), ([29.75, 14.0, 12.5], 3.0), ([15.0, 27.5, 20.0], 3.25)]
+    for x, R in cand:
+        xs.append(x)
+        Rs.append(R)
+    while len(xs) < 9:
+        R = rng.uniform(1.2, 3.5)
+        x = [rng.uniform(0, n[0]), rng.uniform(0, n[1]), rng.uniform(1.5 + R, n[2] - 1.5 - R)]
+        ok = all(np.linalg.norm(np.array(x) - np.array(y)) > R + r + 0.05 for y, r in zip(xs, Rs))
+        if ok:
+            xs.append(x)
+            Rs.append(R)
+    wl = W.Workload("map", W.base_params(nx=n[0], ny=n[1], nz=n[2], max_spheres=len(xs)),
+                    np.array(xs), np.array(Rs), np.full(len(xs), 2.0), np.zeros((len(xs), 3)),
+                    np.zeros((len(xs), 3)), 0)
+    o, g = oracle_domain(wl), gpu_domain(wl, storage=storage)
+    cg, og = g.flags()
+    co, oo = o.flags()
+    assert np.array_equal(cg, co)
+    sol = co == O.SOLID
+    assert sol.sum() > 100 and np.array_equal(og[sol], oo[sol])
+
+
+def test_fixed_sphere_forces_on_random_field():
+    n = (20, 18, 22)
+    _case(f"fixed sphere forces {n}")
+    wl = W.Workload("fixed", W.base_params(nx=n[0], ny=n[1], nz=n[2], nu=0.02, max_spheres=2),
+                    np.array([[9.3, 8.7, 11.2], [2.0, 3.0, 1.0 + 3.1 + 0.3]]), np.array([4.1, 3.1]),
+                    np.array([2.0, 2.0]), np.array([[0.01, -0.02, 0.005], [0.0, 0.0, 0.0]]),
+                    np.array([[0.001, 0.002, -0.003], [0.0, 0.001, 0.0]]), 0)
+    f = random_pdf(n, seed=3, u0=(0.01, 0.0, -0.01))
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    for dom in (o, g):
+        for i in range(2):
+            dom.set_mode(i, O.MODE_FIXED)
+        dom.set_pdf(f)
+    for step in range(6):
+        o.step(1)
+        g.step(1)
+        for i in range(2):
+            so, sg = o.sphere(i), g.sphere(i)
+            scale = np.abs(so["F_raw"]).max()
+            assert np.abs(sg["F_raw"] - so["F_raw"]).max() <= TOL * scale, (step, i)
+            tscale = np.abs(so["T_raw"]).max()
+            assert np.abs(sg["T_raw"] - so["T_raw"]).max() <= TOL * max(tscale, scale)
+    _compare_fields(g, o)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_settling_sphere_32_fp64(seed):
+    wl = W.settling_32(seed)
+    _case(f"settling_32 seed {seed} FP64, {wl.steps} steps")
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    sc = Scales(weight(wl))
+    done = 0
+    for chk in (1, 10, 60, 150, 300):
+        o.step(chk - done)
+        g.step(chk - done)
+        done = chk
+        so = o.sphere(0)
+        e = sphere_errs(g.sphere(0), so, 2 * wl.R[0], sc.update(so))
+        print(f"  step {chk}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_fp"] < 1e-10 and e["w"] < 1e-10, e
+    _compare_fields(g, o)
+
+
+def test_contact_variant_fp64():
+    wl = W.contact_32(0)
+    _case(f"contact_32 FP64, {wl.steps} steps")
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    sc = Scales(weight(wl))
+    saw_contact = saw_lub = False
+    done = 0
+    for chk in (20, 60, 100, 150, 200, 300):
+        o.step(chk - done)
+        g.step(chk - done)
+        done = chk
+        so, sg = o.sphere(0), g.sphere(0)
+        saw_contact |= bool(np.abs(so["F_col"]).max() > 0)
+        saw_lub |= bool(np.abs(so["F_lub"]).max() > 0)
+        e = sphere_errs(sg, so, 2 * wl.R[0], sc.update(so))
+        print(f"  step {chk} gap {so['x'][2] - 1 - wl.R[0]:.4f}",
+              {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10 and e["F_lub"] < 1e-10, e
+    assert saw_contact or saw_lub
+    _compare_fields(g, o)
+
+
+def test_two_spheres_oblique_collision_fp64():
+    n = (40, 24, 24)
+    _case("two spheres colliding, periodic")
+    wl = W.Workload("pair", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.02,
+                                          tc=30.0, max_spheres=2),
+                    np.array([[12.0, 12.1, 11.8], [12.0 + 8.45, 12.9, 12.2]]), np.array([4.0, 4.2]),
+                    np.array([2.0, 3.0]), np.array([[0.04, 0.0, 0.0], [-0.04, 0.0, 0.0]]),
+                    np.zeros((2, 3)), 120)
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    done = 0
+    saw = False
+    sc = [Scales(), Scales()]
+    for chk in (10, 30, 50, 80, 120):
+        o.step(chk - done)
+        g.step(chk - done)
+        done = chk
+        for i in range(2):
+            so, sg = o.sphere(i), g.sphere(i)
+            saw |= bool(np.abs(so["F_col"]).max() > 0)
+            e = sphere_errs(sg, so, 8.0, sc[i].update(so))
+            print(f"  step {chk} sphere {i}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+            assert e["x"] < TOL and e["u"] < 1e-10 and e["w"] < 1e-10 and e["F_col"] < 1e-10, (chk, i, e)
+    assert saw
+    _compare_fields(g, o)
+
+
+def test_prescribed_ramp_and_release():
+    n = (24, 24, 40)
+    _case("prescribed ramp and release")
+    wl = W.Workload("ramp", W.base_params(nx=n[0], ny=n[1], nz=n[2], nu=0.02,
+                                          gravity=(0, 0, -2e-5), max_spheres=1),
+                    np.array([[12.2, 11.9, 24.0]]), np.array([4.0]), np.array([3.0]),
+                    np.zeros((1, 3)), np.zeros((1, 3)), 200,
+                    ramp=dict(u_target=(0.0, 0.0, -0.04), c_acc=10.0, t_st=60.0, release_gap=12.0))
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    done = 0
+    released = False
+    sc = Scales(weight(wl))
+    for chk in (20, 80, 140, 200):
+        o.step(chk - done)
+        g.step(chk - done)
+        done = chk
+        so, sg = o.sphere(0), g.sphere(0)
+        released |= so["mode"] == O.MODE_FREE
+        assert sg["mode"] == so["mode"]
+        e = sphere_errs(sg, so, 8.0, sc.update(so))
+        print(f"  step {chk}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10, (chk, e)
+    assert released
+    _compare_fields(g, o)
+
+
+def test_update_spheres_reconstructs():
+    n = (18, 18, 18)
+    _case("teleport + reconstruction")
+    wl = W.Workload("tele", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 0), nu=0.04,
+                                          max_spheres=1),
+                    np.array([[8.3, 8.9, 9.1]]), np.array([3.6]), np.array([2.0]),
+                    np.array([[0.01, 0.02, 0.0]]), np.array([[0.0, 0.0, 0.01]]), 0)
+    f = random_pdf(n, seed=9, u0=(0.02, 0.0, 0.0))
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    for dom in (o, g):
+        dom.set_mode(0, O.MODE_FIXED)
+        dom.set_pdf(f)
+        dom.step(3)
+    for x in ([9.1, 9.4, 8.2], [17.5, 0.4, 9.0]):  # second one wraps the periodic corner
+        o.update_sphere(0, x=x)
+        g.update_spheres([0], x=np.array([x]))
+        _compare_fields(g, o)
+        o.step(2)
+        g.step(2)
+        _compare_fields(g, o)
+
+
+def test_wide_rows_block_shape():
+    n = (300, 5, 6)  # rows wider than one block, not a multiple of 256
+    _case(f"wide rows {n}")
+    wl = W.Workload("wide", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.05,
+                                          max_spheres=1),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    f = random_pdf(n, seed=21, u0=(0.03, 0.0, 0.0))
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(10)
+    g.step(10)
+    _compare_fields(g, o)
+
+
+@pytest.mark.parametrize("storage,tol_u,tol_f", [(1, 1e-5, 1e-4), (2, 2e-2, 5e-2)])
+def test_reduced_storage_error_vs_oracle(storage, tol_u, tol_f):
+    wl = W.settling_32(0)
+    _case(f"settling_32 storage {storage}")
+    o, g = oracle_domain(wl), gpu_domain(wl, storage=storage)
+    o.step(100)
+    g.step(100)
+    so, sg = o.sphere(0), g.sphere(0)
+    uo, ug = o.field("vel"), g.field("vel")
+    eu = float(np.abs(ug - uo).max() / np.abs(uo).max())
+    ef = float(np.abs(sg["F_fp"] - so["F_fp"]).max() / np.abs(so["F_fp"]).max())
+    ex = float(np.abs(sg["x"] - so["x"]).max() / (2 * wl.R[0]))
+    print(f"  storage {storage}: |du|/|u| {eu:.2e}  |dF|/|F| {ef:.2e}  |dx|/D {ex:.2e}", flush=True)
+    assert eu < tol_u and ef < tol_f
+
+
+def test_empty_domain_and_state_errors():
+    from paper_2003_01490_amd import lbmdem as L
+
+    _case("errors and empty domain")
+    wl = W.Workload("empty", W.base_params(nx=8, ny=8, nz=8, max_spheres=2),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    g = gpu_domain(wl)
+    g.step(3)
+    g.sync()
+    assert g.num_spheres() == 0
+    assert g.try_add_spheres([[4.0, 4.0, 1.5]], 1.0, 2.0) == L.EOVERLAP     # crosses the wall
+    assert g.try_add_spheres([[4.0, 4.0, 4.0]], 9.0, 2.0) == L.EINVAL       # R > max_radius
+    assert g.try_add_spheres([[2.0, 2.0, 3.0], [3.0, 2.0, 3.0]], 0.8, 2.0) == L.EOVERLAP
+    g.add_spheres([[2.0, 2.0, 3.0], [6.0, 6.0, 4.0]], 0.8, 2.0)
+    assert g.try_add_spheres([[4.0, 2.0, 5.0]], 0.5, 2.0) == L.ECAPACITY
+    g.step(2)
+    g.sync()
