@@ -119,7 +119,8 @@ def main():
         for _ in range(3):
             L.device_copy(b, a, nb, dom.stream)
         torch.cuda.synchronize()
-    dom.set_profiling(True)
+    # timed region: HIP events around every sweep launch only (level 1)
+    dom.set_profiling(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(args.steps)
@@ -128,10 +129,12 @@ def main():
     dom.sync()
     elapsed = t1 - t0
     sweep_ms, sweep_n = dom.profile(0)
-    dem_ms, dem_n = dom.profile(1)
-    map_ms, map_n = dom.profile(2)
-    dom.set_profiling(False)
-
+    # per-kernel-group breakdown from a short extra run with every group timed
+    dom.set_profiling(2)
+    dom.step(min(args.steps, 100))
+    dom.sync()
+    brk = {k: dom.profile(j) for j, k in enumerate(("sweep", "dem_claims", "recon_commit_bc"))}
+    dom.set_profiling(0)
     ncell = cfg.nx * cfg.ny * cfg.nz
     flags = dom.field("flags")
     nfluid = int((flags <= 1).sum())
@@ -176,11 +179,7 @@ def main():
             "avg_launch_us": round(sweep_avg_s * 1e6, 3),
         },
         "mflups_fluid": round(nfluid * args.steps / elapsed / 1e6, 2),
-        "kernel_avg_us": {
-            "sweep": round(sweep_ms / max(sweep_n, 1) * 1e3, 3),
-            "dem": round(dem_ms / max(dem_n, 1) * 1e3, 3),
-            "mapping_bc": round(map_ms / max(map_n, 1) * 1e3, 3),
-        },
+        "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 3) for k, (ms, n) in brk.items()},
         "sphere_final": {"z": float(s0["x"][2]), "uz": float(s0["u"][2]), "mode": s0["mode"]},
     }
     if wl.meta:

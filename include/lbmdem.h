@@ -172,7 +172,10 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
 int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f);
 
 /* Kernel timing with HIP events on the domain's stream (for roofline
- * reports).  kernel: 0 fused stream-collide sweep, 1 DEM, 2 mapping + boundary.
+ * reports).  enable: 0 off, 1 the sweep only (each event record adds a small
+ * gap to the queue, so level 1 disturbs the step least), 2 every kernel group.
+ * kernel: 0 fused stream-collide sweep, 1 DEM sub-cycles + mapping claims,
+ * 2 reconstruction + mapping commit + boundary values and force partials.
  * get returns the summed milliseconds and launch count since enabling. */
 int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable);
 int32_t lbmdem_get_profile(lbmdem_domain* dom, int32_t kernel, double* total_ms,

@@ -20,9 +20,14 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 size_t storage_size(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
 
-int zblocks(const lbmdem_config& c) {
-  const int e = 2 * (int)std::ceil(c.max_radius + c.delta_ab) + 6;
-  return std::max(1, std::min(c.nz, e));
+// nominal box extent of a sphere (shell radius, one cell of motion, margins)
+int box_extent(const lbmdem_config& c) { return 2 * (int)std::ceil(c.max_radius + c.delta_ab) + 6; }
+
+int zblocks(const lbmdem_config& c) { return std::max(1, std::min(c.nz, box_extent(c))); }
+
+int rowblocks(const lbmdem_config& c) {
+  const int e = std::min(c.ny, box_extent(c));
+  return std::max(1, (e + COMMIT_ROWS - 1) / COMMIT_ROWS);
 }
 
 struct Layout {
@@ -73,7 +78,7 @@ Layout make_layout(const lbmdem_config& c) {
   L.hist_d = take(24 * P * HIST_SLOTS);
   L.nbr = take(4 * P * NBR_MAX);
   L.nbr_n = take(4 * P);
-  L.partial = take(48 * P * (size_t)zblocks(c));
+  L.partial = take(48 * P * (size_t)zblocks(c) * (size_t)rowblocks(c));
   L.status = take(256);
   L.total = o;
   return L;
@@ -118,7 +123,7 @@ struct lbmdem_domain {
   int failed = 0;
   std::string err;
   std::vector<double> hx, hR;  // host shadow for insertion checks
-  bool prof = false;
+  int prof = 0;  // 1: time the sweep only, 2: every kernel group
   struct Ev {
     hipEvent_t a, b;
     int kind;
@@ -166,9 +171,12 @@ static void harvest(lbmdem_domain* dom) {
   dom->pending.clear();
 }
 
+// Brackets a launch with HIP events on stream s when profiling is on.  Each
+// event record costs the queue a few microseconds, so level 1 brackets only
+// the sweep (kind 0) and level 2 every kernel group.
 template <typename F>
-static void timed(lbmdem_domain* dom, int kind, F&& launch) {
-  if (!dom->prof) {
+static void timed(lbmdem_domain* dom, int kind, hipStream_t s, F&& launch) {
+  if (dom->prof == 0 || (dom->prof == 1 && kind != 0)) {
     launch();
     return;
   }
@@ -177,16 +185,16 @@ static void timed(lbmdem_domain* dom, int kind, F&& launch) {
     harvest(dom);
   }
   lbmdem_domain::Ev ev{get_event(dom), get_event(dom), kind};
-  if (ev.a) (void)hipEventRecord(ev.a, dom->stream);
+  if (ev.a) (void)hipEventRecord(ev.a, s);
   launch();
-  if (ev.b) (void)hipEventRecord(ev.b, dom->stream);
+  if (ev.b) (void)hipEventRecord(ev.b, s);
   if (ev.a && ev.b) dom->pending.push_back(ev);
 }
 
 static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
   dom->stamp += 1;
   dom->d.P = (int)dom->hR.size();
-  timed(dom, 2, [&] { launch_mapping(dom->d, dom->cur, dom->stamp, reconstruct, dom->stream); });
+  timed(dom, 2, dom->stream, [&] { launch_mapping(dom->d, dom->cur, dom->stamp, reconstruct, dom->stream); });
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;
 }
@@ -312,6 +320,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   p.nbr_n = (int*)(base + L.nbr_n);
   d.P = 0;
   d.ZB = zblocks(*cfg);
+  d.RB = rowblocks(*cfg);
   d.partial = (double*)(base + L.partial);
   d.status = (int*)(base + L.status);
   d.n_sub = cfg->n_sub;
@@ -329,6 +338,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.skin = 1.0;
   hipStream_t s = dom->stream;
   const size_t Pm = (size_t)std::max(cfg->max_spheres, 1);
+
   // particle block and status are plain zeros except the free history slots
   int32_t rc = LBMDEM_OK;
   if (hipMemsetAsync(base + L.x, 0, L.total - L.x, s) != hipSuccess ||
@@ -519,11 +529,19 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, con
 int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   if (!dom || nsteps < 0) return LBMDEM_EINVAL;
   if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  dom->d.P = (int)dom->hR.size();
+  // One stream, back to back: the sweep (A -> B), the DEM sub-cycles and the
+  // claims of the new positions, then reconstruction and the boundary pass
+  // that commits the mapping and prepares the next step's links.
   for (int s = 0; s < nsteps; ++s) {
-    timed(dom, 0, [&] { launch_sweep(dom->d, dom->cur, dom->stream); });
+    timed(dom, 0, dom->stream, [&] { launch_sweep(dom->d, dom->cur, dom->stream); });
+    dom->stamp += 1;
+    timed(dom, 1, dom->stream, [&] {
+      launch_dem(dom->d, dom->stream);
+      launch_claim(dom->d, dom->stamp, dom->stream);
+    });
     dom->cur ^= 1;
-    timed(dom, 1, [&] { launch_dem(dom->d, dom->stream); });
-    if (int32_t rc = remap(dom, true)) return rc;
+    timed(dom, 2, dom->stream, [&] { launch_update(dom->d, dom->cur, dom->stamp, true, dom->stream); });
     dom->steps += 1;
   }
   HIPCHK(dom, hipGetLastError());
@@ -636,7 +654,7 @@ int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable) {
   if (!dom) return LBMDEM_EINVAL;
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
   harvest(dom);
-  dom->prof = enable != 0;
+  dom->prof = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
   for (int k = 0; k < 3; ++k) {
     dom->ms[k] = 0.0;
     dom->cnt[k] = 0;

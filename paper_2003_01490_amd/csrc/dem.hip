@@ -51,43 +51,53 @@ __device__ inline void body_vel(const double* u, const double* w, const double* 
   U[2] = u[2] + wr[2];
 }
 
-__device__ inline double min_wall_gap(const DevDomain& d, int i) {
+__device__ inline double min_wall_gap(const DevDomain& d, const DevParticles& p, int i) {
   double g = 1e300;
   const int n[3] = {d.nx, d.ny, d.nz};
   for (int a = 0; a < 3; ++a) {
     if (!d.walls[a]) continue;
-    const double lo = (d.p.x[3 * i + a] - 1.0) - d.p.R[i];
-    const double hi = (((double)n[a] - 1.0) - d.p.x[3 * i + a]) - d.p.R[i];
+    const double lo = (p.x[3 * i + a] - 1.0) - p.R[i];
+    const double hi = (((double)n[a] - 1.0) - p.x[3 * i + a]) - p.R[i];
     g = fmin(g, fmin(lo, hi));
   }
   return g;
 }
 
-__device__ inline void make_sphere_partner(const DevDomain& d, int i, int j, Partner& pt) {
+__device__ __forceinline__ void make_sphere_partner(const DevDomain& d, const DevParticles& p, int i, int j,
+                                                    Partner& pt) {
   double dd[3];
   const int n[3] = {d.nx, d.ny, d.nz};
-  for (int a = 0; a < 3; ++a) dd[a] = min_image(d.p.x[3 * i + a] - d.p.x[3 * j + a], n[a], d.walls[a]);
+  for (int a = 0; a < 3; ++a) dd[a] = min_image(p.x[3 * i + a] - p.x[3 * j + a], n[a], d.walls[a]);
   const double dist = norm3(dd);
   pt.code = j;
   pt.j = j;
   for (int a = 0; a < 3; ++a) pt.n[a] = dd[a] / dist;
-  pt.delta = dist - (d.p.R[i] + d.p.R[j]);
+  pt.delta = dist - (p.R[i] + p.R[j]);
   for (int a = 0; a < 3; ++a) {
-    pt.xcp[a] = d.p.x[3 * i + a] - 0.5 * dd[a];
+    pt.xcp[a] = p.x[3 * i + a] - 0.5 * dd[a];
     pt.rj[a] = 0.5 * dd[a];
   }
 }
 
-__device__ inline void make_wall_partner(const DevDomain& d, int i, int a, int side, Partner& pt) {
-  const int n[3] = {d.nx, d.ny, d.nz};
+__device__ __forceinline__ void make_wall_partner(const DevDomain& d, const DevParticles& p, int i, int a,
+                                                  int side, Partner& pt) {
+  // selects instead of indexing local arrays with the runtime axis, so that
+  // nothing spills to scratch memory
+  const double s = side ? -1.0 : 1.0;
   pt.code = -1 - (2 * a + side);
   pt.j = -1;
-  pt.n[0] = pt.n[1] = pt.n[2] = 0.0;
-  pt.n[a] = side ? -1.0 : 1.0;
-  const double R = d.p.R[i];
-  const double xa = d.p.x[3 * i + a];
-  pt.delta = side ? (((double)n[a] - 1.0) - xa) - R : (xa - 1.0) - R;
-  for (int b = 0; b < 3; ++b) pt.xcp[b] = d.p.x[3 * i + b] - (R + 0.5 * pt.delta) * pt.n[b];
+  pt.n[0] = a == 0 ? s : 0.0;
+  pt.n[1] = a == 1 ? s : 0.0;
+  pt.n[2] = a == 2 ? s : 0.0;
+  const double R = p.R[i];
+  const double x0 = p.x[3 * i], x1 = p.x[3 * i + 1], x2 = p.x[3 * i + 2];
+  const double xa = a == 0 ? x0 : (a == 1 ? x1 : x2);
+  const int na = a == 0 ? d.nx : (a == 1 ? d.ny : d.nz);
+  pt.delta = side ? (((double)na - 1.0) - xa) - R : (xa - 1.0) - R;
+  const double h = R + 0.5 * pt.delta;
+  pt.xcp[0] = x0 - h * pt.n[0];
+  pt.xcp[1] = x1 - h * pt.n[1];
+  pt.xcp[2] = x2 - h * pt.n[2];
   pt.rj[0] = pt.rj[1] = pt.rj[2] = 0.0;
 }
 
@@ -98,7 +108,7 @@ __device__ inline double min_lub_gap(const DevDomain& d, double R) {
   return d.dmin >= 0.0 ? d.dmin : (0.001 + 0.00007 * R) * R;  // Eq. (lubricationGapSize)
 }
 
-__device__ void lubrication(const DevDomain& d, double dmin, const double* n, double delta,
+__device__ __forceinline__ void lubrication(const DevDomain& d, double dmin, const double* n, double delta,
                             const double* ui, const double* wi, double Ri, const double* uj,
                             const double* wj, double Rj, bool wall, double* F, double* T) {
   const double mu = d.nu;
@@ -152,9 +162,8 @@ __device__ void lubrication(const DevDomain& d, double dmin, const double* n, do
 
 // forces on sphere i at the current state; contact: evaluate contacts;
 // upd: write the tangential-spring history
-__device__ void eval_forces(const DevDomain& d, int i, bool contact, bool upd, double dtp,
-                            double* Fout, double* Tout) {
-  const DevParticles& p = d.p;
+__device__ __forceinline__ void eval_forces(const DevDomain& d, const DevParticles& p, int i, bool contact,
+                                            bool upd, double dtp, double* Fout, double* Tout) {
   double Flub[3] = {0, 0, 0}, Tlub[3] = {0, 0, 0}, Fcol[3] = {0, 0, 0}, Tcol[3] = {0, 0, 0};
   const double maxcut = fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr));
   const double* xi = p.x + 3 * i;
@@ -169,7 +178,7 @@ __device__ void eval_forces(const DevDomain& d, int i, bool contact, bool upd, d
   for (int pi = 0; pi < nn + nwalls; ++pi) {
     Partner pt;
     if (pi < nn) {
-      make_sphere_partner(d, i, p.nbr[(size_t)i * NBR_MAX + pi], pt);
+      make_sphere_partner(d, p, i, p.nbr[(size_t)i * NBR_MAX + pi], pt);
     } else {
       int wk = pi - nn, a = 0;
       for (a = 0; a < 3; ++a) {
@@ -177,7 +186,7 @@ __device__ void eval_forces(const DevDomain& d, int i, bool contact, bool upd, d
         if (wk < 2) break;
         wk -= 2;
       }
-      make_wall_partner(d, i, a, wk, pt);
+      make_wall_partner(d, p, i, a, wk, pt);
     }
     const bool is_wall = pt.j < 0;
     const double* uj = is_wall ? zero : p.u + 3 * pt.j;
@@ -280,15 +289,30 @@ __device__ void eval_forces(const DevDomain& d, int i, bool contact, bool upd, d
   }
 }
 
-__global__ __launch_bounds__(256) void k_dem(DevDomain d) {
+__device__ __forceinline__ void dem_body(const DevDomain& d, const DevParticles& p) {
   const int P = d.P;
-  const DevParticles& p = d.p;
   const int n[3] = {d.nx, d.ny, d.nz};
+  // Momentum-exchange sums: one wavefront per sphere; lane l adds the
+  // partials l, l + 64, ... in order, then a fixed shuffle tree combines the
+  // lanes, so the result does not depend on scheduling.
+  {
+    const int nb = d.ZB * d.RB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    for (int i = wave; i < P; i += nwave) {
+      double F[6] = {0, 0, 0, 0, 0, 0};
+      for (int b = lane; b < nb; b += 64)
+        for (int k = 0; k < 6; ++k) F[k] += d.partial[((size_t)i * nb + b) * 6 + k];
+      for (int k = 0; k < 6; ++k) {
+        double v = F[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) p.Fraw[6 * i + k] = v;
+      }
+    }
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    double F[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = 0; b < d.ZB; ++b)
-      for (int k = 0; k < 6; ++k) F[k] += d.partial[((size_t)i * d.ZB + b) * 6 + k];
-    for (int k = 0; k < 6; ++k) p.Fraw[6 * i + k] = F[k];
+    double F[6];
+    for (int k = 0; k < 6; ++k) F[k] = p.Fraw[6 * i + k];
     if (d.force_averaging) {
       if (!p.prev_valid[i])
         for (int k = 0; k < 6; ++k) p.Fprev[6 * i + k] = F[k];
@@ -325,12 +349,12 @@ __global__ __launch_bounds__(256) void k_dem(DevDomain d) {
   const double dtp = 1.0 / (double)d.n_sub;
   for (int sub = 0; sub < d.n_sub; ++sub) {
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
-      if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, i) < p.presc[6 * i + 5]) {
+      if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, p, i) < p.presc[6 * i + 5]) {
         p.mode[i] = MODE_FREE;
         p.old_valid[i] = 0;
       }
       if (p.mode[i] == MODE_FREE && !p.old_valid[i]) {
-        eval_forces(d, i, false, false, dtp, p.Fold + 6 * i, p.Fold + 6 * i + 3);
+        eval_forces(d, p, i, false, false, dtp, p.Fold + 6 * i, p.Fold + 6 * i + 3);
         p.old_valid[i] = 1;
       }
     }
@@ -354,7 +378,7 @@ __global__ __launch_bounds__(256) void k_dem(DevDomain d) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < P; i += blockDim.x)
-      eval_forces(d, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
+      eval_forces(d, p, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
     __syncthreads();
     for (int i = threadIdx.x; i < P; i += blockDim.x) {
       const double* Fn = p.Fnew + 6 * i;
@@ -389,9 +413,93 @@ __global__ __launch_bounds__(256) void k_dem(DevDomain d) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_dem(DevDomain d) { dem_body(d, d.p); }
+
+// Few spheres: their state, contact histories and neighbour lists live in LDS
+// for the whole step, so the sub-cycles (separated by workgroup barriers) do
+// not wait on memory round trips.
+constexpr int DEM_LDS_MAX = 32;
+
+__global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
+  constexpr int PS = DEM_LDS_MAX;
+  __shared__ double sx[3 * PS], su[3 * PS], sw[3 * PS], sR[PS], sm[PS], sI[PS], srho[PS], stp[PS];
+  __shared__ double spresc[6 * PS], sFfp[6 * PS], sFold[6 * PS], sdiag[18 * PS], sFnew[6 * PS];
+  __shared__ double shd[3 * HIST_SLOTS * PS];
+  __shared__ int smode[PS], sold[PS], shid[HIST_SLOTS * PS], snbr[NBR_MAX * PS], snn[PS];
+  const int P = d.P;
+  const DevParticles& g = d.p;
+  for (int t = threadIdx.x; t < P; t += blockDim.x) {
+    for (int a = 0; a < 3; ++a) {
+      sx[3 * t + a] = g.x[3 * t + a];
+      su[3 * t + a] = g.u[3 * t + a];
+      sw[3 * t + a] = g.w[3 * t + a];
+    }
+    sR[t] = g.R[t];
+    sm[t] = g.m[t];
+    sI[t] = g.I[t];
+    srho[t] = g.rho[t];
+    stp[t] = g.tpresc[t];
+    smode[t] = g.mode[t];
+    sold[t] = g.old_valid[t];
+    for (int k = 0; k < 6; ++k) {
+      spresc[6 * t + k] = g.presc[6 * t + k];
+      sFold[6 * t + k] = g.Fold[6 * t + k];
+    }
+    for (int k = 0; k < HIST_SLOTS; ++k) {
+      shid[HIST_SLOTS * t + k] = g.hist_id[(size_t)HIST_SLOTS * t + k];
+      for (int a = 0; a < 3; ++a) shd[3 * (HIST_SLOTS * t + k) + a] = g.hist_d[3 * ((size_t)HIST_SLOTS * t + k) + a];
+    }
+  }
+  __syncthreads();
+  DevParticles l = g;
+  l.x = sx;
+  l.u = su;
+  l.w = sw;
+  l.R = sR;
+  l.m = sm;
+  l.I = sI;
+  l.rho = srho;
+  l.presc = spresc;
+  l.tpresc = stp;
+  l.Ffp = sFfp;
+  l.Fold = sFold;
+  l.diag = sdiag;
+  l.Fnew = sFnew;
+  l.mode = smode;
+  l.old_valid = sold;
+  l.hist_id = shid;
+  l.hist_d = shd;
+  l.nbr = snbr;
+  l.nbr_n = snn;
+  dem_body(d, l);
+  __syncthreads();
+  for (int t = threadIdx.x; t < P; t += blockDim.x) {
+    for (int a = 0; a < 3; ++a) {
+      g.x[3 * t + a] = sx[3 * t + a];
+      g.u[3 * t + a] = su[3 * t + a];
+      g.w[3 * t + a] = sw[3 * t + a];
+    }
+    g.tpresc[t] = stp[t];
+    g.mode[t] = smode[t];
+    g.old_valid[t] = sold[t];
+    for (int k = 0; k < 6; ++k) {
+      g.Ffp[6 * t + k] = sFfp[6 * t + k];
+      g.Fold[6 * t + k] = sFold[6 * t + k];
+    }
+    for (int k = 0; k < 18; ++k) g.diag[18 * t + k] = sdiag[18 * t + k];
+    for (int k = 0; k < HIST_SLOTS; ++k) {
+      g.hist_id[(size_t)HIST_SLOTS * t + k] = shid[HIST_SLOTS * t + k];
+      for (int a = 0; a < 3; ++a) g.hist_d[3 * ((size_t)HIST_SLOTS * t + k) + a] = shd[3 * (HIST_SLOTS * t + k) + a];
+    }
+  }
+}
+
 void launch_dem(const DevDomain& d, hipStream_t s) {
   if (d.P <= 0) return;
-  hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
+  if (d.P <= DEM_LDS_MAX)
+    hipLaunchKernelGGL(k_dem_lds, dim3(1), dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
 }
 
 }  // namespace lbmdem

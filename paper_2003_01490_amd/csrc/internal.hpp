@@ -27,6 +27,7 @@ constexpr uint8_t F_SOLID = 1;
 constexpr uint8_t F_WALL = 2;
 constexpr uint8_t F_SHELL = 4;
 
+constexpr int COMMIT_ROWS = 8;   // y-rows of a box slab per boundary block
 constexpr int HIST_SLOTS = 24;   // contact-history slots per sphere
 constexpr int NBR_MAX = 48;      // neighbour-list capacity per sphere
 
@@ -93,8 +94,9 @@ struct DevDomain {
   uint32_t* shellstamp;
   DevParticles p;
   int P;           // spheres present
-  int ZB;          // mapping blocks per sphere
-  double* partial; // [P][ZB][6]
+  int ZB;          // mapping blocks per sphere along z (slabs)
+  int RB;          // row blocks per slab in the boundary kernel
+  double* partial; // [P][ZB * RB][6]
   int* status;
   // DEM parameters
   int n_sub;
@@ -128,8 +130,12 @@ __device__ inline double min_image(double v, int n, int wall) {
 
 // host-side launchers (implemented in the .hip files)
 void launch_sweep(const DevDomain& d, int cur, hipStream_t s);
+// claim + (reconstruction) + commit/boundary values, in order on one stream
 void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
                     hipStream_t s);
+// the claim kernel alone (needs only the particle positions), and the rest
+void launch_claim(const DevDomain& d, uint32_t stamp, hipStream_t s);
+void launch_update(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s);
 void launch_dem(const DevDomain& d, hipStream_t s);
 void launch_fields(const DevDomain& d, int cur, int field, double* dst, hipStream_t s);
 void launch_set_pdf(const DevDomain& d, int cur, const double* src, hipStream_t s);

@@ -31,6 +31,9 @@
 namespace lbmdem {
 
 enum { S_FLUID = 0, S_SHELL = 1, S_SOLID = 2, S_WALL = 3 };
+// staged neighbour codes relative to the sphere a block works for
+enum { L_FLUID = 0, L_SHELL = 1, L_OWN = 2, L_OTHER = 3, L_WALL = 4 };
+constexpr int STAGE_BYTES = 32768;
 
 struct Box {
   int lo[3];
@@ -79,15 +82,18 @@ __device__ inline double cell_d2(const DevDomain& d, int i, int j, int k, const 
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// state of a cell after the current mapping update (claims of this stamp)
+// state of a cell after the current mapping update (claims of this stamp);
+// the three loads are independent so that they are in flight together
 __device__ inline int new_state(const DevDomain& d, long long c, uint32_t stamp, int* own) {
-  if (d.flags[c] & F_WALL) return S_WALL;
+  const uint8_t fl = d.flags[c];
   const unsigned long long k = d.claim[c];
+  const uint32_t ss = d.shellstamp[c];
+  if (fl & F_WALL) return S_WALL;
   if ((uint32_t)(k >> 32) == stamp) {
     *own = (int)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
     return S_SOLID;
   }
-  return d.shellstamp[c] == stamp ? S_SHELL : S_FLUID;
+  return ss == stamp ? S_SHELL : S_FLUID;
 }
 
 __device__ inline bool is_fluid_state(int s) { return s == S_FLUID || s == S_SHELL; }
@@ -225,20 +231,139 @@ __device__ void reconstruct(const DevDomain& d, T* buf, uint32_t stamp, int ii, 
   }
 }
 
+// Eq. (PDF_reconstruction) for cell c formerly covered by sphere i, computed
+// by one wavefront: lane q (1..18) checks neighbour x + c_q and forms its
+// density and velocity from 19 independent loads; the lanes' values are then
+// combined in q order (the same order as a serial loop) and lane q writes f_q.
+template <typename T>
+__device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, long long c, int i,
+                                 int lane) {
+  const size_t N = (size_t)d.N;
+  const int ii = (int)(c % d.nx), jj = (int)((c / d.nx) % d.ny), kk = (int)(c / ((long long)d.nx * d.ny));
+  bool valid = false;
+  double rn = 0.0, un[3] = {0.0, 0.0, 0.0};
+  if (lane >= 1 && lane < Q) {
+    const long long y = cidx(d, wrapi(ii + CX[lane], d.nx), wrapi(jj + CY[lane], d.ny), wrapi(kk + CZ[lane], d.nz));
+    int o;
+    valid = !(d.flags[y] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, y, stamp, &o));
+    if (valid) {
+      double f[Q];
+#pragma unroll
+      for (int p = 0; p < Q; ++p) f[p] = ldv<T>(buf + (size_t)p * N + y) + WQ[p];
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        rn += f[p];
+        un[0] += f[p] * CX[p];
+        un[1] += f[p] * CY[p];
+        un[2] += f[p] * CZ[p];
+      }
+    }
+  }
+  double rsum = 0.0;
+  int nvalid = 0;
+  for (int q = 1; q < Q; ++q) {
+    const int v = __shfl((int)valid, q, 64);
+    const double r = __shfl(rn, q, 64);
+    if (v) {
+      rsum += r;
+      nvalid += 1;
+    }
+  }
+  const double rb = nvalid > 0 ? rsum / (double)nvalid : 1.0;
+  double rel[3], ut[3];
+  rel[0] = min_image(((double)ii + 0.5) - d.p.x[3 * i], d.nx, d.walls[0]);
+  rel[1] = min_image(((double)jj + 0.5) - d.p.x[3 * i + 1], d.ny, d.walls[1]);
+  rel[2] = min_image(((double)kk + 0.5) - d.p.x[3 * i + 2], d.nz, d.walls[2]);
+  {
+    const double* wv = d.p.w + 3 * i;
+    const double* uv = d.p.u + 3 * i;
+    ut[0] = uv[0] + (wv[1] * rel[2] - wv[2] * rel[1]);
+    ut[1] = uv[1] + (wv[2] * rel[0] - wv[0] * rel[2]);
+    ut[2] = uv[2] + (wv[0] * rel[1] - wv[1] * rel[0]);
+  }
+  double du[3][3];  // du[a][b] = d u_a / d x_b
+  const int axp[3] = {4, 1, 5}, axm[3] = {3, 2, 6};
+#pragma unroll
+  for (int bb = 0; bb < 3; ++bb) {
+    const bool vp = __shfl((int)valid, axp[bb], 64) != 0;
+    const bool vm = __shfl((int)valid, axm[bb], 64) != 0;
+    double up[3], um[3];
+    for (int a = 0; a < 3; ++a) {
+      up[a] = __shfl(un[a], axp[bb], 64);
+      um[a] = __shfl(un[a], axm[bb], 64);
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (vp && vm)
+        du[a][bb] = 0.5 * (up[a] - um[a]);
+      else if (vp)
+        du[a][bb] = up[a] - ut[a];
+      else if (vm)
+        du[a][bb] = ut[a] - um[a];
+      else
+        du[a][bb] = 0.0;
+    }
+  }
+  if (lane < Q) {
+    const int q = lane;
+    const int cq[3] = {CX[q], CY[q], CZ[q]};
+    const double inv3s = rb / (3.0 * d.s_nu);
+    const double cu = cq[0] * ut[0] + cq[1] * ut[1] + cq[2] * ut[2];
+    double second = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int bb = 0; bb < 3; ++bb) {
+        const double Pab = rb * ut[a] * ut[bb] - inv3s * (du[a][bb] + du[bb][a]);
+        const double Hab = (double)(cq[a] * cq[bb]) - (a == bb ? 1.0 / 3.0 : 0.0);
+        second += Pab * Hab;
+      }
+    const double f = WQ[q] * (rb + 3.0 * rb * cu + 4.5 * second);
+    stv<T>(buf + (size_t)q * N + c, f - WQ[q]);
+  }
+}
+
+constexpr int RECON_LIST = 1024;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_recon(DevDomain d, int cur, uint32_t stamp) {
   const int i = blockIdx.x / d.ZB, b = blockIdx.x % d.ZB;
   if (i >= d.P) return;
+  __shared__ long long cand[RECON_LIST];
+  __shared__ int ncand;
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
   Box bx;
   sphere_box(d, i, true, bx);
   T* buf = (T*)d.pdf[cur];
+  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
+  const double xn[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
+  double R2;
+  {
+#pragma clang fp contract(off)
+    const double R = d.p.R[i];
+    R2 = R * R;
+  }
+  // A cell leaves sphere i only if its centre was inside the old ball and is
+  // outside the new one: the same FP64 test both mappings made, so only this
+  // thin shell of cells touches memory.  Cells to rebuild are listed in LDS
+  // and then rebuilt one wavefront each.
   FOR_BOX_CELLS(d, bx, b, d.ZB, {
-    const long long c = cidx(d, ii, jj, kk);
-    if ((d.flags[c] & F_SOLID) && d.owner[c] == i) {
-      int o;
-      if (new_state(d, c, stamp, &o) != S_SOLID) reconstruct<T>(d, buf, stamp, ii, jj, kk, i);
+    if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
+      const long long c = cidx(d, ii, jj, kk);
+      if ((d.flags[c] & F_SOLID) && d.owner[c] == i) {
+        int o;
+        if (new_state(d, c, stamp, &o) != S_SOLID) {
+          const int k = atomicAdd(&ncand, 1);
+          if (k < RECON_LIST)
+            cand[k] = c;
+          else
+            reconstruct<T>(d, buf, stamp, ii, jj, kk, i);  // list full: rebuild here
+        }
+      }
     }
   })
+  __syncthreads();
+  const int n = min(ncand, RECON_LIST);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  for (int e = wave; e < n; e += nwave) reconstruct_wave<T>(d, buf, stamp, cand[e], i, lane);
 }
 
 // smallest root in [0,1] of |r + delta c|^2 = R^2 (x_b = x + delta_q c_q)
@@ -253,8 +378,111 @@ __device__ inline double link_delta(const double* r, const int* c, double R) {
 }
 
 template <typename T>
+struct LinkCtx {
+  const DevDomain& d;
+  T* buf;
+  size_t N;
+  const uint8_t* st;
+  bool staged;
+  int cidx0, HX, HY;
+  int ii, jj, kk;
+  long long yc;
+  int i;
+  uint32_t stamp;
+  const double* xp;
+  const double* up;
+  const double* wp;
+  double R;
+};
+
+// Six directions Q0..Q0+5 of a solid cell y of sphere i: classify the cell
+// x = y - c_q (fluid link, missing link or own solid), issue all PDF loads of
+// the batch, then form the boundary values of Eq. (MEM_CLI) (stored into slot
+// qbar of y), the momentum-exchange forces of Eq. (MEM_Fq) and their torques.
+template <typename T, int Q0>
+__device__ inline void link_batch(const LinkCtx<T>& c, double* acc) {
+  constexpr int NB = 6;
+  const DevDomain& d = c.d;
+  int code[NB];
+  long long xg[NB], xmg[NB];
+  bool cli[NB];
+  double gq[NB], gqb[NB], gm[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int q = Q0 + k;
+    const int cq0 = CX[q], cq1 = CY[q], cq2 = CZ[q];
+    // wall layers shield every non-wall cell, so y - c_q stays in range
+    const int xi = wrapi(c.ii - cq0, d.nx), xj = wrapi(c.jj - cq1, d.ny), xk = wrapi(c.kk - cq2, d.nz);
+    xg[k] = cidx(d, xi, xj, xk);
+    if (c.staged) {
+      code[k] = c.st[c.cidx0 - cq0 - c.HX * (cq1 + c.HY * cq2)];
+    } else {
+      int zo = -1;
+      const int zs = new_state(d, xg[k], c.stamp, &zo);
+      code[k] = zs == S_WALL ? L_WALL : (zs == S_SOLID ? (zo == c.i ? L_OWN : L_OTHER) : (zs == S_SHELL ? L_SHELL : L_FLUID));
+    }
+    cli[k] = false;
+    xmg[k] = 0;
+    gq[k] = gqb[k] = gm[k] = 0.0;
+    if (code[k] <= L_SHELL) {
+      if (d.boundary == 0) {
+        xmg[k] = cidx(d, wrapi(xi - cq0, d.nx), wrapi(xj - cq1, d.ny), wrapi(xk - cq2, d.nz));
+        if (c.staged) {
+          cli[k] = c.st[c.cidx0 - 2 * cq0 - c.HX * (2 * cq1 + c.HY * 2 * cq2)] <= L_SHELL;
+        } else {
+          int mo;
+          cli[k] = is_fluid_state(new_state(d, xmg[k], c.stamp, &mo));
+        }
+      }
+      gq[k] = ldv<T>(c.buf + (size_t)q * c.N + xg[k]);
+      gqb[k] = ldv<T>(c.buf + (size_t)OPP[q] * c.N + xg[k]);
+      if (cli[k]) gm[k] = ldv<T>(c.buf + (size_t)q * c.N + xmg[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int q = Q0 + k;
+    if (code[k] == L_OWN) continue;
+    const int cq[3] = {CX[q], CY[q], CZ[q]};
+    double Fq[3], arm[3];
+    if (code[k] <= L_SHELL) {
+      const int xi = wrapi(c.ii - cq[0], d.nx), xj = wrapi(c.jj - cq[1], d.ny), xk = wrapi(c.kk - cq[2], d.nz);
+      double r[3];
+      r[0] = min_image(((double)xi + 0.5) - c.xp[0], d.nx, d.walls[0]);
+      r[1] = min_image(((double)xj + 0.5) - c.xp[1], d.ny, d.walls[1]);
+      r[2] = min_image(((double)xk + 0.5) - c.xp[2], d.nz, d.walls[2]);
+      const double dl = link_delta(r, cq, c.R);
+      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * cq[a];
+      double ub[3];
+      ub[0] = c.up[0] + (c.wp[1] * arm[2] - c.wp[2] * arm[1]);
+      ub[1] = c.up[1] + (c.wp[2] * arm[0] - c.wp[0] * arm[2]);
+      ub[2] = c.up[2] + (c.wp[0] * arm[1] - c.wp[1] * arm[0]);
+      const double dd = cli[k] ? dl : 0.5;
+      double val = gq[k];
+      if (cli[k]) val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (gm[k] - gqb[k]);
+      val -= 4.0 / (1.0 + 2.0 * dd) * WQ[q] * 3.0 * (ub[0] * cq[0] + ub[1] * cq[1] + ub[2] * cq[2]);
+      stv<T>(c.buf + (size_t)OPP[q] * c.N + c.yc, val);
+      const double fq = gq[k] + WQ[q], fb = val + WQ[q];
+      for (int a = 0; a < 3; ++a) Fq[a] = (cq[a] - ub[a]) * fq - (-cq[a] - ub[a]) * fb;
+    } else {
+      // wall or another sphere's solid: missing link, F_q = 2 w_q c_q
+      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * WQ[q] * cq[a];
+      arm[0] = min_image(((double)c.ii + 0.5) - c.xp[0], d.nx, d.walls[0]) - 0.5 * cq[0];
+      arm[1] = min_image(((double)c.jj + 0.5) - c.xp[1], d.ny, d.walls[1]) - 0.5 * cq[1];
+      arm[2] = min_image(((double)c.kk + 0.5) - c.xp[2], d.nz, d.walls[2]) - 0.5 * cq[2];
+    }
+    acc[0] += Fq[0];
+    acc[1] += Fq[1];
+    acc[2] += Fq[2];
+    acc[3] += arm[1] * Fq[2] - arm[2] * Fq[1];
+    acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
+    acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t stamp, int nwall) {
-  const int nsb = d.P * d.ZB;
+  const int nsb = d.P * d.ZB * d.RB;
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
   if ((int)blockIdx.x >= nsb) {
@@ -296,96 +524,134 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t s
       uw[2] = d.wall_u_hi[2];
     }
     const long long y = cidx(d, ii, jj, kk);
+    // all neighbour states first, then the PDFs of the fluid ones, then the
+    // stores: two memory round trips per wall cell instead of one per direction
+    bool ok[Q];
+    long long xs[Q];
+    uint8_t sfl[Q];
+    unsigned long long sk[Q];
+#pragma unroll
     for (int q = 1; q < Q; ++q) {
       int xi = ii + CX[q], xj = jj + CY[q], xk = kk + CZ[q];
-      if (d.walls[0] ? (xi < 0 || xi >= d.nx) : false) continue;
-      if (d.walls[1] ? (xj < 0 || xj >= d.ny) : false) continue;
-      if (d.walls[2] ? (xk < 0 || xk >= d.nz) : false) continue;
-      xi = wrapi(xi, d.nx);
-      xj = wrapi(xj, d.ny);
-      xk = wrapi(xk, d.nz);
-      const long long x = cidx(d, xi, xj, xk);
-      int o;
-      if (!is_fluid_state(new_state(d, x, stamp, &o))) continue;
-      const double v = ldv<T>(buf + (size_t)OPP[q] * N + x) +
-                       6.0 * WQ[q] * (uw[0] * CX[q] + uw[1] * CY[q] + uw[2] * CZ[q]);
-      stv<T>(buf + (size_t)q * N + y, v);
+      ok[q] = !((d.walls[0] && (xi < 0 || xi >= d.nx)) || (d.walls[1] && (xj < 0 || xj >= d.ny)) ||
+                (d.walls[2] && (xk < 0 || xk >= d.nz)));
+      xs[q] = cidx(d, wrapi(xi, d.nx), wrapi(xj, d.ny), wrapi(xk, d.nz));
+      if (ok[q]) {
+        sfl[q] = d.flags[xs[q]];
+        sk[q] = d.claim[xs[q]];
+      }
     }
+    double v[Q];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      // fluid after this update: not a wall, not claimed by this stamp
+      ok[q] = ok[q] && !(sfl[q] & F_WALL) && (uint32_t)(sk[q] >> 32) != stamp;
+      if (ok[q]) v[q] = ldv<T>(buf + (size_t)OPP[q] * N + xs[q]);
+    }
+#pragma unroll
+    for (int q = 1; q < Q; ++q)
+      if (ok[q])
+        stv<T>(buf + (size_t)q * N + y, v[q] + 6.0 * WQ[q] * (uw[0] * CX[q] + uw[1] * CY[q] + uw[2] * CZ[q]));
     return;
   }
-  const int i = blockIdx.x / d.ZB, b = blockIdx.x % d.ZB;
+  const int nbs = d.ZB * d.RB;
+  const int i = blockIdx.x / nbs, b = blockIdx.x % nbs;
+  const int bz = b / d.RB, brow = b % d.RB;
   Box bx;
   sphere_box(d, i, true, bx);
   const double xp[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
+  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
   const double up[3] = {d.p.u[3 * i], d.p.u[3 * i + 1], d.p.u[3 * i + 2]};
   const double wp[3] = {d.p.w[3 * i], d.p.w[3 * i + 1], d.p.w[3 * i + 2]};
   const double R = d.p.R[i];
+  double R2, rs2;
+  {
+#pragma clang fp contract(off)
+    const double rs = R + d.delta_ab;
+    R2 = R * R;
+    rs2 = rs * rs;
+  }
+  // States of the slab's cells and of a 2-cell halo (the CLI needs x - c_q of
+  // the fluid cell x = y - c_q) are staged in LDS, so link detection needs no
+  // dependent global loads; boxes too large for LDS take the global path.
+  // A block works on row chunks of COMMIT_ROWS rows of the box slabs
+  // (slab bz, bz + ZB, ...; chunk brow, brow + RB, ...).
+  const int EX = bx.ext[0], EY = bx.ext[1], HX = EX + 4, HY = COMMIT_ROWS + 4;
+  const bool staged = HX * HY * 5 <= STAGE_BYTES;
+  __shared__ uint8_t st[STAGE_BYTES];
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  FOR_BOX_CELLS(d, bx, b, d.ZB, {
-    const long long yc = cidx(d, ii, jj, kk);
-    int own = -1;
-    const int ns = new_state(d, yc, stamp, &own);
-    if (ns != S_WALL) {
-      d.flags[yc] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
-      if (ns == S_SOLID) d.owner[yc] = own;
-      if (ns == S_SOLID && own == i) {
-        for (int q = 1; q < Q; ++q) {
-          const int cq[3] = {CX[q], CY[q], CZ[q]};
-          // wall layers shield every non-wall cell, so y - c_q stays in range
-          const int xi = wrapi(ii - cq[0], d.nx), xj = wrapi(jj - cq[1], d.ny),
-                    xk = wrapi(kk - cq[2], d.nz);
-          const long long x = cidx(d, xi, xj, xk);
-          int zo = -1;
-          const int zs = new_state(d, x, stamp, &zo);
-          double Fq[3], arm[3];
-          if (is_fluid_state(zs)) {
-            double r[3];
-            r[0] = min_image(((double)xi + 0.5) - xp[0], d.nx, d.walls[0]);
-            r[1] = min_image(((double)xj + 0.5) - xp[1], d.ny, d.walls[1]);
-            r[2] = min_image(((double)xk + 0.5) - xp[2], d.nz, d.walls[2]);
-            const double dl = link_delta(r, cq, R);
-            for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * cq[a];
-            double ub[3];
-            ub[0] = up[0] + (wp[1] * arm[2] - wp[2] * arm[1]);
-            ub[1] = up[1] + (wp[2] * arm[0] - wp[0] * arm[2]);
-            ub[2] = up[2] + (wp[0] * arm[1] - wp[1] * arm[0]);
-            const int qb = OPP[q];
-            const double gq = ldv<T>(buf + (size_t)q * N + x);
-            const double gqb = ldv<T>(buf + (size_t)qb * N + x);
-            bool cli = false;
-            long long xm = 0;
-            if (d.boundary == 0) {
-              const int mi = wrapi(xi - cq[0], d.nx), mj = wrapi(xj - cq[1], d.ny),
-                        mk = wrapi(xk - cq[2], d.nz);
-              xm = cidx(d, mi, mj, mk);
-              int mo;
-              cli = is_fluid_state(new_state(d, xm, stamp, &mo));
+  for (int sl = bz; sl < bx.ext[2]; sl += d.ZB) {
+    const int kz = bx.lo[2] + sl;
+    const int kk = d.walls[2] ? kz : wrapmod(kz, d.nz);
+    // does this plane cut the new solid ball of sphere i?
+    const double dzc = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]);
+    const bool cuts = dzc * dzc <= R2;
+    for (int ry0 = brow * COMMIT_ROWS; ry0 < EY; ry0 += d.RB * COMMIT_ROWS) {
+      const int nrow = min(COMMIT_ROWS, EY - ry0);
+      if (staged && cuts) {
+        __syncthreads();
+        // four entries per thread and pass, all loads issued before any use
+        const int NS = HX * HY * 5;
+        for (int t0 = threadIdx.x; t0 < NS; t0 += 4 * blockDim.x) {
+          bool in[4];
+          uint8_t fl[4];
+          unsigned long long kc[4];
+          uint32_t ss[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * blockDim.x;
+            const int hx = t % HX, r = t / HX, hy = r % HY, hz = r / HY;
+            const int gx = bx.lo[0] - 2 + hx, gy = bx.lo[1] + ry0 - 2 + hy, gz = kz - 2 + hz;
+            in[u] = t < NS && (!d.walls[0] || (gx >= 0 && gx < d.nx)) &&
+                    (!d.walls[1] || (gy >= 0 && gy < d.ny)) && (!d.walls[2] || (gz >= 0 && gz < d.nz));
+            if (in[u]) {
+              const long long c = cidx(d, wrapmod(gx, d.nx), wrapmod(gy, d.ny), wrapmod(gz, d.nz));
+              fl[u] = d.flags[c];
+              kc[u] = d.claim[c];
+              ss[u] = d.shellstamp[c];
             }
-            const double dd = cli ? dl : 0.5;
-            double val = gq;
-            if (cli) val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (ldv<T>(buf + (size_t)q * N + xm) - gqb);
-            val -= 4.0 / (1.0 + 2.0 * dd) * WQ[q] * 3.0 * (ub[0] * cq[0] + ub[1] * cq[1] + ub[2] * cq[2]);
-            stv<T>(buf + (size_t)qb * N + yc, val);
-            const double fq = gq + WQ[q], fb = val + WQ[q];
-            for (int a = 0; a < 3; ++a) Fq[a] = (cq[a] - ub[a]) * fq - (-cq[a] - ub[a]) * fb;
-          } else if (zs == S_WALL || (zs == S_SOLID && zo != i)) {
-            for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * WQ[q] * cq[a];
-            arm[0] = min_image(((double)ii + 0.5) - xp[0], d.nx, d.walls[0]) - 0.5 * cq[0];
-            arm[1] = min_image(((double)jj + 0.5) - xp[1], d.ny, d.walls[1]) - 0.5 * cq[1];
-            arm[2] = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]) - 0.5 * cq[2];
-          } else {
-            continue;
           }
-          acc[0] += Fq[0];
-          acc[1] += Fq[1];
-          acc[2] += Fq[2];
-          acc[3] += arm[1] * Fq[2] - arm[2] * Fq[1];
-          acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
-          acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * blockDim.x;
+            if (t >= NS) continue;
+            uint8_t code = L_WALL;
+            if (in[u] && !(fl[u] & F_WALL)) {
+              if ((uint32_t)(kc[u] >> 32) == stamp) {
+                const int o = (int)(0xFFFFFFFFu - (uint32_t)(kc[u] & 0xFFFFFFFFull));
+                code = o == i ? L_OWN : L_OTHER;
+              } else {
+                code = ss[u] == stamp ? L_SHELL : L_FLUID;
+              }
+            }
+            st[t] = code;
+          }
         }
+        __syncthreads();
+      }
+      const int ncell = EX * nrow;
+      for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+        const int tx = t % EX, ty = t / EX;
+        const int ii = d.walls[0] ? bx.lo[0] + tx : wrapmod(bx.lo[0] + tx, d.nx);
+        const int jj = d.walls[1] ? bx.lo[1] + ry0 + ty : wrapmod(bx.lo[1] + ry0 + ty, d.ny);
+        // only cells within the old or new shell ball of i can change through i
+        const double dn2 = cell_d2(d, ii, jj, kk, xp);
+        if (!(dn2 <= rs2) && !(cell_d2(d, ii, jj, kk, xo) <= rs2)) continue;
+        const long long yc = cidx(d, ii, jj, kk);
+        int own = -1;
+        const int ns = new_state(d, yc, stamp, &own);
+        if (ns == S_WALL) continue;
+        d.flags[yc] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
+        if (ns == S_SOLID) d.owner[yc] = own;
+        if (!(ns == S_SOLID && own == i)) continue;
+        const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
+        const LinkCtx<T> lc{d, buf, N, st, staged, cidx0, HX, HY, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
+        link_batch<T, 1>(lc, acc);
+        link_batch<T, 7>(lc, acc);
+        link_batch<T, 13>(lc, acc);
       }
     }
-  })
+  }
   // fixed-order block reduction: wavefront shuffles, then across wavefronts
   __shared__ double red[6][8];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -399,7 +665,7 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t s
     double v = 0.0;
     const int nw = (blockDim.x + 63) >> 6;
     for (int w8 = 0; w8 < nw; ++w8) v += red[threadIdx.x][w8];
-    d.partial[((size_t)i * d.ZB + b) * 6 + threadIdx.x] = v;
+    d.partial[((size_t)i * nbs + b) * 6 + threadIdx.x] = v;
   }
 }
 
@@ -412,27 +678,35 @@ static int wall_cell_count(const DevDomain& d) {
   return n;
 }
 
-template <typename T>
-static void launch_mapping_t(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
-                             hipStream_t s) {
+void launch_claim(const DevDomain& d, uint32_t stamp, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0) {
-    hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, stamp);
-    if (reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, cur, stamp);
-  }
+  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, stamp);
+}
+
+template <typename T>
+static void launch_update_t(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
+                            hipStream_t s) {
+  const int nsb = d.P * d.ZB;
+  if (nsb > 0 && reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, cur, stamp);
+  const int ncb = nsb * d.RB;
   const int nwall = wall_cell_count(d);
   const int wblocks = (nwall + 255) / 256;
-  if (nsb + wblocks > 0)
-    hipLaunchKernelGGL(k_commit<T>, dim3(nsb + wblocks), dim3(256), 0, s, d, cur, stamp, nwall);
+  if (ncb + wblocks > 0)
+    hipLaunchKernelGGL(k_commit<T>, dim3(ncb + wblocks), dim3(256), 0, s, d, cur, stamp, nwall);
+}
+
+void launch_update(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s) {
+  if (d.storage == 0)
+    launch_update_t<double>(d, cur, stamp, reconstruct, s);
+  else if (d.storage == 1)
+    launch_update_t<float>(d, cur, stamp, reconstruct, s);
+  else
+    launch_update_t<__half>(d, cur, stamp, reconstruct, s);
 }
 
 void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s) {
-  if (d.storage == 0)
-    launch_mapping_t<double>(d, cur, stamp, reconstruct, s);
-  else if (d.storage == 1)
-    launch_mapping_t<float>(d, cur, stamp, reconstruct, s);
-  else
-    launch_mapping_t<__half>(d, cur, stamp, reconstruct, s);
+  launch_claim(d, stamp, s);
+  launch_update(d, cur, stamp, reconstruct, s);
 }
 
 }  // namespace lbmdem

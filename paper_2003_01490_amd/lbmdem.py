@@ -262,8 +262,9 @@ class Domain:
         self._check(lib().lbmdem_set_pdf(self.h, _dp(f)))
 
     # --- profiling --------------------------------------------------------
-    def set_profiling(self, on: bool):
-        self._check(lib().lbmdem_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, level: int):
+        """0 off, 1 time the sweep only, 2 time every kernel group."""
+        self._check(lib().lbmdem_set_profiling(self.h, int(level)))
 
     def profile(self, kernel: int):
         ms = C.c_double()
