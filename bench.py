@@ -56,6 +56,25 @@ def make_workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
+def traffic_record(workload: str, storage: str):
+    """HBM bytes per sweep launch measured with hardware counters (profiles/),
+    valid only while the sweep source is the one that was measured."""
+    import glob
+    import hashlib
+    import re
+
+    src = os.path.join(ROOT, "paper_2003_01490_amd", "csrc", "sweep.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    tag = {"f64": "FP64", "f32": "FP32", "f16": "FP16"}[storage]
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "pmc_traffic_*.md"))):
+        for block in re.findall(r"```json\n(.*?)\n```", open(f).read(), re.S):
+            rec = json.loads(block)
+            if rec.get("sweep_src_sha256") == sha and rec.get("workload", "").startswith(workload) \
+                    and rec["workload"].endswith(tag):
+                return rec["bytes_per_launch"], os.path.relpath(f, ROOT)
+    return None, None
+
+
 def cpu_baseline(wl, steps):
     """The oracle, single-threaded, on `steps` coupled steps of the same
     lattice and spheres."""
@@ -143,6 +162,7 @@ def main():
     bytes_per_launch = dom.sweep_bytes()
     achieved = bytes_per_launch / sweep_avg_s / 1e9
     s0 = dom.sphere(0)
+    traffic, traffic_src = traffic_record(wl.name, args.storage)
 
     result = {
         "metric": METRIC,
@@ -174,7 +194,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(sweep_avg_s * 1e6, 3),
         },
