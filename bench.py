@@ -75,8 +75,20 @@ def traffic_record(workload: str, storage: str):
     return None, None
 
 
+def cpu_sample(name, wl, seed):
+    """Workload the oracle is timed on: the same one where a few steps take
+    seconds; for the dense suspensions its 96^3 sub-problem at the same solid
+    fraction (the oracle's brute-force mapping visits every cell for every
+    sphere)."""
+    from paper_2003_01490_amd import workloads as W
+
+    if name.startswith("dense"):
+        return W.dense(seed, n=96, count=156), "96^3 sub-problem with 156 spheres D=12 (same solid fraction)"
+    return wl, "the same workload"
+
+
 def cpu_baseline(wl, steps):
-    """The oracle, single-threaded, on `steps` coupled steps of the same
+    """The oracle, single-threaded, on `steps` coupled steps of the given
     lattice and spheres."""
     import oracle as O
 
@@ -103,7 +115,7 @@ def main():
     ap.add_argument("--workload", default="sphere_wall")
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
@@ -207,7 +219,9 @@ def main():
         result["config"]["params"] = {k: (round(v, 6) if isinstance(v, float) else v)
                                       for k, v in wl.meta.items()}
     if not args.no_cpu_baseline:
-        mlups_cpu, dt = cpu_baseline(wl, args.cpu_steps)
+        swl, what = cpu_sample(args.workload, wl, args.seed)
+        mlups_cpu, dt = cpu_baseline(swl, args.cpu_steps)
+        sn = (swl.params["nx"], swl.params["ny"], swl.params["nz"])
         try:
             cpu = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
             model = [l.split(":", 1)[1].strip() for l in cpu.splitlines() if "Model name" in l][:1]
@@ -218,8 +232,8 @@ def main():
             "unit": "MLUPS",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"{args.cpu_steps} coupled steps of the same {cfg.nx}x{cfg.ny}x{cfg.nz} workload "
-                      f"from the same initial state ({dt:.1f} s, single thread)",
+            "sample": f"{args.cpu_steps} coupled steps of {what} ({sn[0]}x{sn[1]}x{sn[2]}) from its "
+                      f"initial state ({dt:.1f} s, single thread)",
             "cpu": model[0] if model else platform.processor(),
         }
     print(json.dumps(result))

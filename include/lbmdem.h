@@ -53,7 +53,7 @@ enum {
   LBMDEM_EDEVICE = -3,   /* HIP runtime error                              */
   LBMDEM_EOVERLAP = -4,  /* sphere overlaps a wall or another sphere       */
   LBMDEM_EUNSTABLE = -5, /* non-finite particle state detected             */
-  LBMDEM_ECAPACITY = -6, /* max_spheres / contact or neighbour slots full  */
+  LBMDEM_ECAPACITY = -6, /* max_spheres / contact, neighbour or bin slots full */
   LBMDEM_ESTATE = -7     /* domain already failed                          */
 };
 
@@ -95,6 +95,11 @@ typedef struct lbmdem_config {
   int32_t lub_mask;         /* bit0 normal, bit1 tangential translation, bit2 rotation */
   int32_t max_spheres;      /* capacity, sizes the device region                 */
   double max_radius;        /* largest sphere radius that will be added          */
+  int32_t dem_kernel;       /* DEM sub-cycle kernel: 0 automatic (one workgroup up
+                               to 256 spheres, else grid-wide), 1 one workgroup
+                               (all-pairs neighbour search), 2 grid-wide
+                               cooperative launch (binned neighbour search);
+                               results are identical                              */
 } lbmdem_config;
 
 typedef struct lbmdem_domain lbmdem_domain;
@@ -159,6 +164,14 @@ int32_t lbmdem_num_spheres(const lbmdem_domain* dom);
  * 15 F_tot 18 T_tot (total of the last sub-step) 21 F_lub 24 T_lub 27 F_col
  * 30 T_col 33 mode 34 R 35 rho 36 F_raw 39 T_raw (resolved, not averaged). */
 int32_t lbmdem_get_sphere_state(lbmdem_domain* dom, int32_t id, double* out);
+
+/* Synchronising copy of the states of n spheres (ids[s], or sphere s when ids
+ * is NULL) into host arrays of 3n doubles each: positions, velocities,
+ * angular velocities, averaged resolved force and torque (F_fp, T_fp of
+ * Sec. 4.2) and total force and torque of the last sub-cycle.  Any output
+ * pointer may be NULL to skip that quantity. */
+int32_t lbmdem_get_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, double* x, double* u,
+                           double* w, double* F_fp, double* T_fp, double* F_tot, double* T_tot);
 
 /* Synchronising copy of a whole-lattice field (LBMDEM_FIELD_*) to dst (host,
  * or device when dst_is_device != 0) of `bytes` bytes; non-fluid cells read 0

@@ -23,17 +23,48 @@ size_t storage_size(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 :
 // nominal box extent of a sphere (shell radius, one cell of motion, margins)
 int box_extent(const lbmdem_config& c) { return 2 * (int)std::ceil(c.max_radius + c.delta_ab) + 6; }
 
-int zblocks(const lbmdem_config& c) { return std::max(1, std::min(c.nz, box_extent(c))); }
+// Mapping blocks per sphere: slabs (z) times row chunks (y).  Few spheres get
+// many blocks each so that the launch fills the chip; with many spheres one
+// block per sphere already does, and fewer partials keep the DEM prologue short.
+constexpr int MAP_BLOCKS_TARGET = 2048;
+
+int zblocks(const lbmdem_config& c) {
+  const int per = (MAP_BLOCKS_TARGET + std::max(c.max_spheres, 1) - 1) / std::max(c.max_spheres, 1);
+  return std::max(1, std::min(std::min(c.nz, box_extent(c)), per));
+}
 
 int rowblocks(const lbmdem_config& c) {
   const int e = std::min(c.ny, box_extent(c));
-  return std::max(1, (e + COMMIT_ROWS - 1) / COMMIT_ROWS);
+  const int full = std::max(1, (e + COMMIT_ROWS - 1) / COMMIT_ROWS);
+  const long long have = (long long)std::max(c.max_spheres, 1) * zblocks(c);
+  const int per = (int)std::max(1LL, (MAP_BLOCKS_TARGET + have - 1) / have);
+  return std::min(full, per);
+}
+
+// uniform bins of the grid-wide neighbour search: edge at least the largest
+// centre distance of two listed neighbours (2 R_max + cut-off + skin), grown
+// if the count would exceed a few per sphere
+constexpr double NBR_SKIN = 1.0;
+
+void bin_dims(const lbmdem_config& c, int* nb) {
+  const int n[3] = {c.nx, c.ny, c.nz};
+  double h = 2.0 * c.max_radius + std::max(c.cut_n, std::max(c.cut_tt, c.cut_tr)) + NBR_SKIN;
+  const double limit = std::max(4096.0, 4.0 * (double)std::max(c.max_spheres, 1));
+  for (;;) {
+    double tot = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      nb[a] = std::max(1, (int)std::floor((double)n[a] / h));
+      tot *= nb[a];
+    }
+    if (tot <= limit) return;
+    h *= 1.25;
+  }
 }
 
 struct Layout {
   size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
-      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, partial, status;
+      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, barrier, partial, status;
   size_t total;
 };
 
@@ -78,6 +109,13 @@ Layout make_layout(const lbmdem_config& c) {
   L.hist_d = take(24 * P * HIST_SLOTS);
   L.nbr = take(4 * P * NBR_MAX);
   L.nbr_n = take(4 * P);
+  L.x2 = take(24 * P);
+  L.u2 = take(24 * P);
+  L.w2 = take(24 * P);
+  int nb[3];
+  bin_dims(c, nb);
+  L.bins = take(4 * (size_t)nb[0] * nb[1] * nb[2] * (1 + BIN_CAP));
+  L.barrier = take(256);
   L.partial = take(48 * P * (size_t)zblocks(c) * (size_t)rowblocks(c));
   L.status = take(256);
   L.total = o;
@@ -103,6 +141,7 @@ const char* check_config(const lbmdem_config* c) {
   if (!(c->poisson_ratio >= 0.0 && c->poisson_ratio < 1.0)) return "poisson_ratio must lie in [0, 1)";
   if (!(c->friction >= 0.0)) return "friction must be non-negative";
   if (!(c->cut_n > 0.0 && c->cut_tt > 0.0 && c->cut_tr > 0.0)) return "cut-offs must be positive";
+  if (c->dem_kernel < 0 || c->dem_kernel > 2) return "dem_kernel must be 0..2";
   return nullptr;
 }
 
@@ -132,6 +171,8 @@ struct lbmdem_domain {
   std::vector<hipEvent_t> spare;
   double ms[3] = {0, 0, 0};
   int64_t cnt[3] = {0, 0, 0};
+  int grid_cap = 0;                   // co-resident blocks of the grid-wide DEM kernel
+  unsigned long long bar_base = 0;    // arrivals at the grid-wide barriers so far
 };
 
 static int32_t fail(lbmdem_domain* dom, int32_t code, const std::string& msg) {
@@ -226,6 +267,7 @@ int32_t lbmdem_config_init(lbmdem_config* c) {
   c->lub_mask = 7;
   c->max_spheres = 16;
   c->max_radius = 12.0;
+  c->dem_kernel = 0;
   return LBMDEM_OK;
 }
 
@@ -318,6 +360,12 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   p.hist_d = (double*)(base + L.hist_d);
   p.nbr = (int*)(base + L.nbr);
   p.nbr_n = (int*)(base + L.nbr_n);
+  p.x2 = (double*)(base + L.x2);
+  p.u2 = (double*)(base + L.u2);
+  p.w2 = (double*)(base + L.w2);
+  bin_dims(*cfg, d.bins.n);
+  d.bins.cell = (int*)(base + L.bins);
+  d.barrier = (unsigned long long*)(base + L.barrier);
   d.P = 0;
   d.ZB = zblocks(*cfg);
   d.RB = rowblocks(*cfg);
@@ -335,7 +383,8 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.cut_tr = cfg->cut_tr;
   d.lub_mask = cfg->lub_mask;
   d.nu = cfg->nu;
-  d.skin = 1.0;
+  d.skin = NBR_SKIN;
+  dom->grid_cap = dem_grid_capacity();
   hipStream_t s = dom->stream;
   const size_t Pm = (size_t)std::max(cfg->max_spheres, 1);
 
@@ -536,10 +585,15 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     timed(dom, 0, dom->stream, [&] { launch_sweep(dom->d, dom->cur, dom->stream); });
     dom->stamp += 1;
+    hipError_t e = hipSuccess;
     timed(dom, 1, dom->stream, [&] {
-      launch_dem(dom->d, dom->stream);
+      e = launch_dem(dom->d, dom->cfg.dem_kernel, dom->grid_cap, &dom->bar_base, dom->stream);
       launch_claim(dom->d, dom->stamp, dom->stream);
     });
+    if (e != hipSuccess) {
+      dom->failed = 1;
+      return fail(dom, LBMDEM_EDEVICE, std::string("DEM launch failed: ") + hipGetErrorString(e));
+    }
     dom->cur ^= 1;
     timed(dom, 2, dom->stream, [&] { launch_update(dom->d, dom->cur, dom->stamp, true, dom->stream); });
     dom->steps += 1;
@@ -559,7 +613,11 @@ int32_t lbmdem_sync(lbmdem_domain* dom) {
   }
   if (st & (ST_HIST_FULL | ST_NBR_FULL)) {
     dom->failed = 1;
-    return fail(dom, LBMDEM_ECAPACITY, "contact-history or neighbour slots exhausted");
+    return fail(dom, LBMDEM_ECAPACITY, "contact-history, neighbour-list or bin slots exhausted");
+  }
+  if (st & ST_BARRIER) {
+    dom->failed = 1;
+    return fail(dom, LBMDEM_EDEVICE, "a grid-wide barrier of the DEM kernel timed out");
   }
   return dom->failed ? LBMDEM_ESTATE : LBMDEM_OK;
 }
@@ -587,6 +645,42 @@ int32_t lbmdem_get_sphere_state(lbmdem_domain* dom, int32_t id, double* out) {
   out[34] = rr[0];
   out[35] = rr[1];
   for (int k = 0; k < 6; ++k) out[36 + k] = fr[k];
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_get_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, double* x, double* u,
+                           double* w, double* F_fp, double* T_fp, double* F_tot, double* T_tot) {
+  if (!dom || n < 0) return LBMDEM_EINVAL;
+  const int32_t P = (int32_t)dom->hR.size();
+  if (!ids && n > P) return fail(dom, LBMDEM_EINVAL, "n exceeds the number of spheres");
+  for (int32_t s = 0; ids && s < n; ++s)
+    if (ids[s] < 0 || ids[s] >= P) return fail(dom, LBMDEM_EINVAL, "bad sphere id");
+  if (n == 0) return LBMDEM_OK;
+  const DevParticles& p = dom->d.p;
+  hipStream_t st = dom->stream;
+  std::vector<double> hx, hu, hw, hf, hd;
+  auto pull = [&](std::vector<double>& h, const double* src, size_t per) -> hipError_t {
+    h.resize(per * (size_t)P);
+    return hipMemcpyAsync(h.data(), src, 8 * per * (size_t)P, hipMemcpyDeviceToHost, st);
+  };
+  if (x) HIPCHK(dom, pull(hx, p.x, 3));
+  if (u) HIPCHK(dom, pull(hu, p.u, 3));
+  if (w) HIPCHK(dom, pull(hw, p.w, 3));
+  if (F_fp || T_fp) HIPCHK(dom, pull(hf, p.Ffp, 6));
+  if (F_tot || T_tot) HIPCHK(dom, pull(hd, p.diag, 18));
+  HIPCHK(dom, hipStreamSynchronize(st));
+  for (int32_t s = 0; s < n; ++s) {
+    const size_t i = (size_t)(ids ? ids[s] : s);
+    for (int a = 0; a < 3; ++a) {
+      if (x) x[3 * s + a] = hx[3 * i + a];
+      if (u) u[3 * s + a] = hu[3 * i + a];
+      if (w) w[3 * s + a] = hw[3 * i + a];
+      if (F_fp) F_fp[3 * s + a] = hf[6 * i + a];
+      if (T_fp) T_fp[3 * s + a] = hf[6 * i + 3 + a];
+      if (F_tot) F_tot[3 * s + a] = hd[18 * i + a];
+      if (T_tot) T_tot[3 * s + a] = hd[18 * i + 3 + a];
+    }
+  }
   return LBMDEM_OK;
 }
 

@@ -1,11 +1,11 @@
 // Discrete element part of one time step (Alg. 1, DEM sub-cycles), FP64.
 //
 // Prologue: per-sphere sum of the momentum-exchange partials written by the
-// boundary kernel (fixed order: slab blocks ascending), averaging with the
-// previous step (Sec. 4.2; the first step averages with itself), copy of the
-// positions the mapping starts from, and a neighbour list per sphere
-// (candidates whose gap is below the largest lubrication cut-off plus a skin).
-// Then n_sub sub-cycles with dt_p = 1/n_sub and F_fp held constant:
+// boundary kernel (fixed order), averaging with the previous step (Sec. 4.2;
+// the first step averages with itself), copy of the positions the mapping
+// starts from, and a neighbour list per sphere (candidates whose gap is below
+// the largest lubrication cut-off plus a skin, ascending ids).  Then n_sub
+// sub-cycles with dt_p = 1/n_sub and F_fp held constant:
 //   release of prescribed spheres below their gap; velocity-Verlet start force
 //   for newly free spheres; Eq. (velocity_verlet_1); lubrication (Sec. 3.1,
 //   step function on the raw gap, magnitude on max(gap, delta_min)), contacts
@@ -14,7 +14,14 @@
 //   V (rho_p - rho_f) g; Eq. (velocity_verlet_2) and its rotational analogue.
 // Forces are gathered per sphere (each sphere sums over its own partners), so
 // nothing is scattered and the pair terms come out antisymmetric exactly.
-// One workgroup; the sub-cycles are separated by workgroup barriers.
+//
+// Two kernels.  Few spheres: one workgroup, sub-cycles separated by workgroup
+// barriers (with state, histories and lists in LDS up to DEM_LDS_MAX spheres).
+// Many spheres: one thread per sphere over a cooperative grid; neighbours are
+// found through uniform bins, and x, u, w alternate between two buffers every
+// sub-cycle (positions are advanced into the other buffer, then forces read
+// the new positions and the old velocities and write the new velocities into
+// the other buffer), so each sub-cycle needs only two grid-wide barriers.
 #include "internal.hpp"
 
 #include <climits>
@@ -289,128 +296,158 @@ __device__ __forceinline__ void eval_forces(const DevDomain& d, const DevParticl
   }
 }
 
+// Momentum-exchange sum of sphere i by one wavefront: lane l adds the
+// partials l, l + 64, ... in order, then a fixed shuffle tree combines the
+// lanes, so the result does not depend on scheduling.  Lane 0 then averages
+// with the previous step and pins the positions the mapping starts from.
+__device__ __forceinline__ void resolved_force(const DevDomain& d, const DevParticles& p, int i, int lane) {
+  const int nb = d.ZB * d.RB;
+  double F[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = lane; b < nb; b += 64)
+    for (int k = 0; k < 6; ++k) F[k] += d.partial[((size_t)i * nb + b) * 6 + k];
+  for (int k = 0; k < 6; ++k) {
+    double v = F[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    F[k] = v;
+  }
+  if (lane != 0) return;
+  for (int k = 0; k < 6; ++k) p.Fraw[6 * i + k] = F[k];
+  if (d.force_averaging) {
+    if (!p.prev_valid[i])
+      for (int k = 0; k < 6; ++k) p.Fprev[6 * i + k] = F[k];
+    for (int k = 0; k < 6; ++k) {
+      p.Ffp[6 * i + k] = 0.5 * (F[k] + p.Fprev[6 * i + k]);
+      p.Fprev[6 * i + k] = F[k];
+    }
+    p.prev_valid[i] = 1;
+  } else {
+    for (int k = 0; k < 6; ++k) p.Ffp[6 * i + k] = F[k];
+  }
+  for (int a = 0; a < 3; ++a) p.xmap[3 * i + a] = p.x[3 * i + a];
+}
+
+// gap between spheres i and j (minimum image); the neighbour test of both
+// kernels, so that they list the same partners
+__device__ __forceinline__ double pair_gap(const DevDomain& d, const DevParticles& p, int i, int j) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+  double dd[3];
+  for (int a = 0; a < 3; ++a) dd[a] = min_image(p.x[3 * i + a] - p.x[3 * j + a], n[a], d.walls[a]);
+  return norm3(dd) - (p.R[i] + p.R[j]);
+}
+
+__device__ __forceinline__ double list_range(const DevDomain& d) {
+  return fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr)) + d.skin;
+}
+
+// release of a prescribed sphere below its gap; start force of a newly free one
+__device__ __forceinline__ void release_and_start(const DevDomain& d, const DevParticles& p, int i, double dtp) {
+  if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, p, i) < p.presc[6 * i + 5]) {
+    p.mode[i] = MODE_FREE;
+    p.old_valid[i] = 0;
+  }
+  if (p.mode[i] == MODE_FREE && !p.old_valid[i]) {
+    eval_forces(d, p, i, false, false, dtp, p.Fold + 6 * i, p.Fold + 6 * i + 3);
+    p.old_valid[i] = 1;
+  }
+}
+
+// Eq. (velocity_verlet_1) (free), x + dt_p u (prescribed), unchanged (fixed);
+// periodic axes wrap.  xo may alias p.x + 3 i.
+__device__ __forceinline__ void advance_position(const DevDomain& d, const DevParticles& p, int i, double dtp,
+                                                 double* xo) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+  const double* x = p.x + 3 * i;
+  if (p.mode[i] == MODE_FREE) {
+    const double c2 = dtp * dtp / (2.0 * p.m[i]);
+    for (int a = 0; a < 3; ++a) xo[a] = (x[a] + dtp * p.u[3 * i + a]) + c2 * p.Fold[6 * i + a];
+  } else if (p.mode[i] == MODE_PRESCRIBED) {
+    for (int a = 0; a < 3; ++a) xo[a] = x[a] + dtp * p.u[3 * i + a];
+  } else {
+    for (int a = 0; a < 3; ++a) xo[a] = x[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (d.walls[a]) continue;
+    const double L = (double)n[a];
+    if (xo[a] < 0.0)
+      xo[a] += L;
+    else if (xo[a] >= L)
+      xo[a] -= L;
+  }
+}
+
+// Eq. (velocity_verlet_2) and its rotational analogue from F_old and the new
+// force in p.Fnew; the ramp of Eq. (artificial_acceleration) for prescribed
+// spheres.  uo, wo may alias p.u + 3 i, p.w + 3 i.
+__device__ __forceinline__ void advance_velocity(const DevDomain& d, const DevParticles& p, int i, double dtp,
+                                                 double* uo, double* wo) {
+  const double* Fn = p.Fnew + 6 * i;
+  double* dg = p.diag + 18 * i;
+  for (int k = 0; k < 6; ++k) dg[k] = Fn[k];
+  if (p.mode[i] == MODE_FREE) {
+    const double cu = dtp / (2.0 * p.m[i]), cw = dtp / (2.0 * p.I[i]);
+    for (int a = 0; a < 3; ++a) {
+      uo[a] = p.u[3 * i + a] + cu * (p.Fold[6 * i + a] + Fn[a]);
+      wo[a] = p.w[3 * i + a] + cw * (p.Fold[6 * i + 3 + a] + Fn[3 + a]);
+      p.Fold[6 * i + a] = Fn[a];
+      p.Fold[6 * i + 3 + a] = Fn[3 + a];
+    }
+  } else if (p.mode[i] == MODE_PRESCRIBED) {
+    p.tpresc[i] += dtp;
+    const double ramp = 1.0 - exp(-p.presc[6 * i + 3] * p.tpresc[i] / p.presc[6 * i + 4]);
+    for (int a = 0; a < 3; ++a) {
+      uo[a] = p.presc[6 * i + a] * ramp;
+      wo[a] = 0.0;
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      uo[a] = p.u[3 * i + a];
+      wo[a] = p.w[3 * i + a];
+    }
+  }
+}
+
+__device__ __forceinline__ void health_check(const DevDomain& d, const DevParticles& p, int i) {
+  bool ok = true;
+  for (int a = 0; a < 3; ++a)
+    ok = ok && isfinite(p.x[3 * i + a]) && isfinite(p.u[3 * i + a]) && isfinite(p.w[3 * i + a]);
+  if (!ok) atomicOr(d.status, ST_NONFINITE);
+}
+
 __device__ __forceinline__ void dem_body(const DevDomain& d, const DevParticles& p) {
   const int P = d.P;
-  const int n[3] = {d.nx, d.ny, d.nz};
-  // Momentum-exchange sums: one wavefront per sphere; lane l adds the
-  // partials l, l + 64, ... in order, then a fixed shuffle tree combines the
-  // lanes, so the result does not depend on scheduling.
   {
-    const int nb = d.ZB * d.RB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    for (int i = wave; i < P; i += nwave) {
-      double F[6] = {0, 0, 0, 0, 0, 0};
-      for (int b = lane; b < nb; b += 64)
-        for (int k = 0; k < 6; ++k) F[k] += d.partial[((size_t)i * nb + b) * 6 + k];
-      for (int k = 0; k < 6; ++k) {
-        double v = F[k];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) p.Fraw[6 * i + k] = v;
-      }
-    }
+    for (int i = wave; i < P; i += nwave) resolved_force(d, p, i, lane);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    double F[6];
-    for (int k = 0; k < 6; ++k) F[k] = p.Fraw[6 * i + k];
-    if (d.force_averaging) {
-      if (!p.prev_valid[i])
-        for (int k = 0; k < 6; ++k) p.Fprev[6 * i + k] = F[k];
-      for (int k = 0; k < 6; ++k) {
-        p.Ffp[6 * i + k] = 0.5 * (F[k] + p.Fprev[6 * i + k]);
-        p.Fprev[6 * i + k] = F[k];
-      }
-      p.prev_valid[i] = 1;
-    } else {
-      for (int k = 0; k < 6; ++k) p.Ffp[6 * i + k] = F[k];
-    }
-    for (int a = 0; a < 3; ++a) p.xmap[3 * i + a] = p.x[3 * i + a];
-  }
-  // neighbour list for this step, partners ascending
-  const double maxcut = fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr));
+  // neighbour list for this step by all pairs, partners ascending
+  const double range = list_range(d);
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
     int cnt = 0;
     for (int j = 0; j < P; ++j) {
-      if (j == i) continue;
-      double dd[3];
-      for (int a = 0; a < 3; ++a) dd[a] = min_image(p.x[3 * i + a] - p.x[3 * j + a], n[a], d.walls[a]);
-      const double gap = norm3(dd) - (p.R[i] + p.R[j]);
-      if (gap < maxcut + d.skin) {
-        if (cnt < NBR_MAX)
-          p.nbr[(size_t)i * NBR_MAX + cnt] = j;
-        else
-          atomicOr(d.status, ST_NBR_FULL);
-        cnt++;
-      }
+      if (j == i || !(pair_gap(d, p, i, j) < range)) continue;
+      if (cnt < NBR_MAX)
+        p.nbr[(size_t)i * NBR_MAX + cnt] = j;
+      else
+        atomicOr(d.status, ST_NBR_FULL);
+      cnt++;
     }
     p.nbr_n[i] = cnt < NBR_MAX ? cnt : NBR_MAX;
   }
   __syncthreads();
   const double dtp = 1.0 / (double)d.n_sub;
   for (int sub = 0; sub < d.n_sub; ++sub) {
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-      if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, p, i) < p.presc[6 * i + 5]) {
-        p.mode[i] = MODE_FREE;
-        p.old_valid[i] = 0;
-      }
-      if (p.mode[i] == MODE_FREE && !p.old_valid[i]) {
-        eval_forces(d, p, i, false, false, dtp, p.Fold + 6 * i, p.Fold + 6 * i + 3);
-        p.old_valid[i] = 1;
-      }
-    }
+    for (int i = threadIdx.x; i < P; i += blockDim.x) release_and_start(d, p, i, dtp);
     __syncthreads();
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-      double* x = p.x + 3 * i;
-      if (p.mode[i] == MODE_FREE) {
-        const double c2 = dtp * dtp / (2.0 * p.m[i]);
-        for (int a = 0; a < 3; ++a) x[a] = (x[a] + dtp * p.u[3 * i + a]) + c2 * p.Fold[6 * i + a];
-      } else if (p.mode[i] == MODE_PRESCRIBED) {
-        for (int a = 0; a < 3; ++a) x[a] = x[a] + dtp * p.u[3 * i + a];
-      }
-      for (int a = 0; a < 3; ++a) {
-        if (d.walls[a]) continue;
-        const double L = (double)n[a];
-        if (x[a] < 0.0)
-          x[a] += L;
-        else if (x[a] >= L)
-          x[a] -= L;
-      }
-    }
+    for (int i = threadIdx.x; i < P; i += blockDim.x) advance_position(d, p, i, dtp, p.x + 3 * i);
     __syncthreads();
     for (int i = threadIdx.x; i < P; i += blockDim.x)
       eval_forces(d, p, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
     __syncthreads();
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-      const double* Fn = p.Fnew + 6 * i;
-      double* dg = p.diag + 18 * i;
-      for (int k = 0; k < 6; ++k) dg[k] = Fn[k];
-      if (p.mode[i] == MODE_FREE) {
-        const double cu = dtp / (2.0 * p.m[i]), cw = dtp / (2.0 * p.I[i]);
-        for (int a = 0; a < 3; ++a) {
-          p.u[3 * i + a] = p.u[3 * i + a] + cu * (p.Fold[6 * i + a] + Fn[a]);
-          p.w[3 * i + a] = p.w[3 * i + a] + cw * (p.Fold[6 * i + 3 + a] + Fn[3 + a]);
-          p.Fold[6 * i + a] = Fn[a];
-          p.Fold[6 * i + 3 + a] = Fn[3 + a];
-        }
-      } else if (p.mode[i] == MODE_PRESCRIBED) {
-        // Eq. (artificial_acceleration)
-        p.tpresc[i] += dtp;
-        const double ramp = 1.0 - exp(-p.presc[6 * i + 3] * p.tpresc[i] / p.presc[6 * i + 4]);
-        for (int a = 0; a < 3; ++a) {
-          p.u[3 * i + a] = p.presc[6 * i + a] * ramp;
-          p.w[3 * i + a] = 0.0;
-        }
-      }
-    }
+    for (int i = threadIdx.x; i < P; i += blockDim.x) advance_velocity(d, p, i, dtp, p.u + 3 * i, p.w + 3 * i);
     __syncthreads();
   }
-  // device-side health check of the particle state
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    bool ok = true;
-    for (int a = 0; a < 3; ++a)
-      ok = ok && isfinite(p.x[3 * i + a]) && isfinite(p.u[3 * i + a]) && isfinite(p.w[3 * i + a]);
-    if (!ok) atomicOr(d.status, ST_NONFINITE);
-  }
+  for (int i = threadIdx.x; i < P; i += blockDim.x) health_check(d, p, i);
 }
 
 __global__ __launch_bounds__(256) void k_dem(DevDomain d) { dem_body(d, d.p); }
@@ -419,6 +456,8 @@ __global__ __launch_bounds__(256) void k_dem(DevDomain d) { dem_body(d, d.p); }
 // for the whole step, so the sub-cycles (separated by workgroup barriers) do
 // not wait on memory round trips.
 constexpr int DEM_LDS_MAX = 32;
+// automatic choice: above this many spheres the grid-wide kernel
+constexpr int DEM_GRID_MIN = 256;
 
 __global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
   constexpr int PS = DEM_LDS_MAX;
@@ -494,12 +533,216 @@ __global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
   }
 }
 
-void launch_dem(const DevDomain& d, hipStream_t s) {
-  if (d.P <= 0) return;
-  if (d.P <= DEM_LDS_MAX)
-    hipLaunchKernelGGL(k_dem_lds, dim3(1), dim3(256), 0, s, d);
+// ---------------------------------------------------------------------------
+// Grid-wide kernel for many spheres.
+
+// Barrier over all blocks of a cooperative launch: a monotonic arrival counter
+// (the host passes the count the launch starts from).  Every thread fences at
+// device scope on both sides, so the writes before the barrier are visible to
+// all blocks after it.  The wait is bounded: if it gives up (which a
+// cooperative launch should make impossible) the status word says so and the
+// kernel still runs to its end.
+__device__ __forceinline__ void grid_barrier(const DevDomain& d, unsigned long long& target, int* broken) {
+  target += gridDim.x;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(d.barrier, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (!*broken && __hip_atomic_load(d.barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1u << 22)) {
+        atomicOr(d.status, ST_BARRIER);
+        *broken = 1;
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+__device__ __forceinline__ int bin_index(const DevDomain& d, const double* x, int* b) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int nb = d.bins.n[a];
+    int k = (int)floor(x[a] * (double)nb / (double)n[a]);
+    b[a] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
+  }
+  return b[0] + d.bins.n[0] * (b[1] + d.bins.n[1] * b[2]);
+}
+
+__device__ __forceinline__ void bin_insert(const DevDomain& d, const DevParticles& p, int i) {
+  const double* x = p.x + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    atomicOr(d.status, ST_NONFINITE);
+    return;
+  }
+  int b[3];
+  int* c = d.bins.cell + (size_t)bin_index(d, x, b) * (1 + BIN_CAP);
+  const int k = atomicAdd(c, 1);
+  if (k < BIN_CAP)
+    c[1 + k] = i;
   else
-    hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
+    atomicOr(d.status, ST_NBR_FULL);
+}
+
+// Bins along one axis that can hold partners of a sphere in bin b: the three
+// around it (wrapped on periodic axes), or every bin when there are fewer than
+// three.  Entry e of axis_count(nb) entries; false if it lies beyond a wall.
+__device__ __forceinline__ int axis_count(int nb) { return nb < 3 ? nb : 3; }
+__device__ __forceinline__ bool axis_bin(int b, int nb, bool wall, int e, int* k) {
+  if (nb < 3) {
+    *k = e;
+    return true;
+  }
+  int v = b + e - 1;
+  if (v < 0 || v >= nb) {
+    if (wall) return false;
+    v = v < 0 ? v + nb : v - nb;
+  }
+  *k = v;
+  return true;
+}
+
+// the neighbour test of dem_body over the candidates of the surrounding bins,
+// kept sorted by id, so both kernels produce the same list
+__device__ __forceinline__ void binned_neighbours(const DevDomain& d, const DevParticles& p, int i) {
+  const double* x = p.x + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    p.nbr_n[i] = 0;
+    return;
+  }
+  const double range = list_range(d);
+  int b[3];
+  bin_index(d, x, b);
+  const int n0 = d.bins.n[0], n1 = d.bins.n[1], n2 = d.bins.n[2];
+  int* out = p.nbr + (size_t)i * NBR_MAX;
+  int cnt = 0;
+  for (int ez = 0; ez < axis_count(n2); ++ez) {
+    int kz;
+    if (!axis_bin(b[2], n2, d.walls[2], ez, &kz)) continue;
+    for (int ey = 0; ey < axis_count(n1); ++ey) {
+      int ky;
+      if (!axis_bin(b[1], n1, d.walls[1], ey, &ky)) continue;
+      for (int ex = 0; ex < axis_count(n0); ++ex) {
+        int kx;
+        if (!axis_bin(b[0], n0, d.walls[0], ex, &kx)) continue;
+        const int* c = d.bins.cell + (size_t)(kx + n0 * (ky + n1 * kz)) * (1 + BIN_CAP);
+        const int m = min(c[0], BIN_CAP);
+        for (int e = 0; e < m; ++e) {
+          const int j = c[1 + e];
+          if (j == i || !(pair_gap(d, p, i, j) < range)) continue;
+          if (cnt < NBR_MAX) {
+            int pos = cnt;
+            while (pos > 0 && out[pos - 1] > j) {
+              out[pos] = out[pos - 1];
+              --pos;
+            }
+            out[pos] = j;
+          } else {
+            atomicOr(d.status, ST_NBR_FULL);
+          }
+          cnt++;
+        }
+      }
+    }
+  }
+  p.nbr_n[i] = cnt < NBR_MAX ? cnt : NBR_MAX;
+}
+
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsigned long long base) {
+  __shared__ int broken;
+  if (threadIdx.x == 0) broken = 0;
+  __syncthreads();
+  unsigned long long target = base;
+  const int P = d.P;
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gstride = gridDim.x * blockDim.x;
+  const DevParticles p = d.p;
+  {
+    const int lane = threadIdx.x & 63;
+    for (int i = gtid >> 6; i < P; i += gstride >> 6) {
+      resolved_force(d, p, i, lane);
+      if (lane == 0) bin_insert(d, p, i);
+    }
+  }
+  grid_barrier(d, target, &broken);
+  for (int i = gtid; i < P; i += gstride) binned_neighbours(d, p, i);
+  grid_barrier(d, target, &broken);
+  const int nbins = d.bins.n[0] * d.bins.n[1] * d.bins.n[2];
+  const double dtp = 1.0 / (double)d.n_sub;
+  for (int sub = 0; sub < d.n_sub; ++sub) {
+    const bool odd = sub & 1;  // state in the second buffers
+    double* const x0 = odd ? p.x2 : p.x;
+    double* const u0 = odd ? p.u2 : p.u;
+    double* const w0 = odd ? p.w2 : p.w;
+    double* const x1 = odd ? p.x : p.x2;
+    double* const u1 = odd ? p.u : p.u2;
+    double* const w1 = odd ? p.w : p.w2;
+    if (sub == 0)  // the lists are built: clear the bins for the next step
+      for (int k = gtid; k < nbins; k += gstride) d.bins.cell[(size_t)k * (1 + BIN_CAP)] = 0;
+    DevParticles a = p;  // state at the start of the sub-cycle
+    a.x = x0;
+    a.u = u0;
+    a.w = w0;
+    for (int i = gtid; i < P; i += gstride) {
+      release_and_start(d, a, i, dtp);
+      advance_position(d, a, i, dtp, x1 + 3 * i);
+    }
+    grid_barrier(d, target, &broken);
+    DevParticles b = a;  // new positions, old velocities
+    b.x = x1;
+    for (int i = gtid; i < P; i += gstride) {
+      eval_forces(d, b, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
+      advance_velocity(d, b, i, dtp, u1 + 3 * i, w1 + 3 * i);
+    }
+    grid_barrier(d, target, &broken);
+  }
+  for (int i = gtid; i < P; i += gstride) {
+    if (d.n_sub & 1)
+      for (int a = 0; a < 3; ++a) {
+        p.x[3 * i + a] = p.x2[3 * i + a];
+        p.u[3 * i + a] = p.u2[3 * i + a];
+        p.w[3 * i + a] = p.w2[3 * i + a];
+      }
+    health_check(d, p, i);
+  }
+}
+
+int dem_grid_capacity() {
+  int dev = 0, ncu = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_dem_grid),
+                                                   DEM_GRID_THREADS, 0) != hipSuccess)
+    return 0;
+  return nb * ncu;
+}
+
+// barriers of one grid-wide launch: two in the prologue, two per sub-cycle
+static unsigned long long grid_barriers(const DevDomain& d) { return 2ull + 2ull * (unsigned long long)d.n_sub; }
+
+hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
+                      hipStream_t s) {
+  if (d.P <= 0) return hipSuccess;
+  const bool grid = kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN);
+  if (!grid) {
+    if (d.P <= DEM_LDS_MAX)
+      hipLaunchKernelGGL(k_dem_lds, dim3(1), dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
+    return hipGetLastError();
+  }
+  if (grid_cap <= 0) return hipErrorInvalidConfiguration;
+  const int want = (d.P + DEM_GRID_THREADS - 1) / DEM_GRID_THREADS;
+  const int blocks = want < grid_cap ? want : grid_cap;
+  DevDomain dd = d;
+  unsigned long long base = *barrier_base;
+  void* args[] = {&dd, &base};
+  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_dem_grid), dim3(blocks),
+                                            dim3(DEM_GRID_THREADS), args, 0, s);
+  if (e == hipSuccess) *barrier_base += (unsigned long long)blocks * grid_barriers(d);
+  return e;
 }
 
 }  // namespace lbmdem

@@ -39,6 +39,9 @@ constexpr int MODE_FIXED = 2;
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_HIST_FULL = 2;
 constexpr int ST_NBR_FULL = 4;
+constexpr int ST_BARRIER = 8;    // a grid-wide barrier gave up waiting
+
+constexpr int BIN_CAP = 15;      // sphere ids per neighbour-search bin (+1 count)
 
 // D3Q19 velocities in the order fixed by rows 2-4 of the MRT moment matrix
 // (App. A of the paper), weights 1/3, 1/18, 1/36 and opposite directions.
@@ -75,6 +78,16 @@ struct DevParticles {
   double* hist_d; // [P][HIST_SLOTS][3] tangential spring
   int* nbr;       // [P][NBR_MAX] candidate partners (ascending)
   int* nbr_n;     // [P]
+  double* x2;     // [P][3] second buffers of x, u, w: the grid-wide DEM
+  double* u2;     //        kernel alternates between the two every sub-cycle
+  double* w2;
+};
+
+// uniform bins of the grid-wide neighbour search: edge >= the largest centre
+// distance at which two spheres can be neighbours
+struct DevBins {
+  int n[3];       // bins per axis
+  int* cell;      // [n0 n1 n2][1 + BIN_CAP]: count, then ids
 };
 
 struct DevDomain {
@@ -106,6 +119,8 @@ struct DevDomain {
   int lub_mask;
   double nu;
   double skin;     // neighbour-list skin
+  DevBins bins;
+  unsigned long long* barrier;  // arrival counter of the grid-wide barriers
 };
 
 __host__ __device__ inline long long cidx(const DevDomain& d, int i, int j, int k) {
@@ -136,7 +151,15 @@ void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruc
 // the claim kernel alone (needs only the particle positions), and the rest
 void launch_claim(const DevDomain& d, uint32_t stamp, hipStream_t s);
 void launch_update(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s);
-void launch_dem(const DevDomain& d, hipStream_t s);
+// DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 grid-wide
+// (cooperative).  *barrier_base is the arrival count the grid barriers start
+// from; it is advanced by the arrivals of the launch.
+// grid_cap: co-resident blocks of the grid-wide kernel (dem_grid_capacity()).
+hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
+                      hipStream_t s);
+// co-resident blocks of the grid-wide DEM kernel on the current device
+int dem_grid_capacity();
+constexpr int DEM_GRID_THREADS = 128;
 void launch_fields(const DevDomain& d, int cur, int field, double* dst, hipStream_t s);
 void launch_set_pdf(const DevDomain& d, int cur, const double* src, hipStream_t s);
 void launch_fill_claims(const DevDomain& d, hipStream_t s);

@@ -47,6 +47,7 @@ class Config(C.Structure):
         ("cut_n", C.c_double), ("cut_tt", C.c_double), ("cut_tr", C.c_double),
         ("lub_mask", C.c_int32), ("max_spheres", C.c_int32),
         ("max_radius", C.c_double),
+        ("dem_kernel", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ def lib():
         "lbmdem_sync": (C.c_int32, [vp]),
         "lbmdem_num_spheres": (C.c_int32, [vp]),
         "lbmdem_get_sphere_state": (C.c_int32, [vp, C.c_int32, dp]),
+        "lbmdem_get_spheres": (C.c_int32, [vp, C.c_int32, ip, dp, dp, dp, dp, dp, dp, dp]),
         "lbmdem_get_field": (C.c_int32, [vp, C.c_int32, vp, C.c_size_t, C.c_int32]),
         "lbmdem_set_pdf": (C.c_int32, [vp, dp]),
         "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
@@ -223,6 +225,19 @@ class Domain:
                     F_col=out[27:30].copy(), T_col=out[30:33].copy(),
                     mode=int(out[33]), R=out[34], rho=out[35],
                     F_raw=out[36:39].copy(), T_raw=out[39:42].copy())
+
+    def spheres(self, ids=None) -> dict:
+        """States of many spheres at once (all when ids is None): arrays of
+        shape (n, 3) for x, u, w, F_fp, T_fp, F_tot, T_tot."""
+        if ids is None:
+            n, idp = self.num_spheres(), None
+        else:
+            ids = np.ascontiguousarray(ids, dtype=np.int32)
+            n, idp = len(ids), ids.ctypes.data_as(C.POINTER(C.c_int32))
+        keys = ("x", "u", "w", "F_fp", "T_fp", "F_tot", "T_tot")
+        out = {k: np.zeros((n, 3)) for k in keys}
+        self._check(lib().lbmdem_get_spheres(self.h, n, idp, *[_dp(out[k]) for k in keys]))
+        return out
 
     # --- time stepping ----------------------------------------------------
     def step(self, n=1):

@@ -17,7 +17,9 @@ Workloads:
                     Eq. (artificial_acceleration) one diameter above the wall.
   dense           - cubic lattice with z walls, equal spheres placed by seeded
                     random sequential addition with a surface gap >= 1 to
-                    every other sphere and wall.
+                    every other sphere and wall (optionally smaller, and with
+                    seeded Gaussian velocities so that lubrication and
+                    contacts occur within a few hundred steps).
 """
 from __future__ import annotations
 
@@ -111,8 +113,9 @@ def sphere_wall(seed: int = 0, nx: int = 128, ny: int = 128, nz: int = 256, D: f
 
 def dense(seed: int = 0, n: int = 96, count: int = 156, D: float = 12.0, rho_r: float = 2.0,
           nu: float = 0.02, g: float = 2e-6, min_gap: float = 1.0, steps: int = 100,
-          nxyz: tuple | None = None) -> Workload:
-    """Random sequential addition of equal spheres (periodic x, y; z walls)."""
+          nxyz: tuple | None = None, u_rms: float = 0.0) -> Workload:
+    """Random sequential addition of equal spheres (periodic x, y; z walls).
+    ``u_rms`` > 0 draws N(0, u_rms) velocity components after the placement."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = nxyz if nxyz else (n, n, n)
     R = D / 2.0
@@ -150,7 +153,9 @@ def dense(seed: int = 0, n: int = 96, count: int = 156, D: float = 12.0, rho_r: 
             grid.setdefault(key, []).append(len(pts))
             pts.append(c)
     x = np.array(pts)
+    u = rng.normal(0.0, u_rms, (count, 3)) if u_rms > 0 else np.zeros((count, 3))
     p = base_params(nx=nx, ny=ny, nz=nz, nu=nu, gravity=(0.0, 0.0, -g), max_spheres=count)
     frac = count * (4.0 / 3.0) * math.pi * R ** 3 / (nx * ny * nz)
-    return Workload("dense", p, x, np.full(count, R), np.full(count, rho_r), np.zeros((count, 3)),
-                    np.zeros((count, 3)), steps, meta=dict(seed=seed, solid_fraction=frac))
+    return Workload("dense", p, x, np.full(count, R), np.full(count, rho_r), u,
+                    np.zeros((count, 3)), steps,
+                    meta=dict(seed=seed, solid_fraction=frac, min_gap=min_gap, u_rms=u_rms))

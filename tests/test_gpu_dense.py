@@ -1,0 +1,209 @@
+"""Many spheres: the GPU path against the FP64 oracle, and the two DEM kernels
+(one workgroup with an all-pairs neighbour search; grid-wide with binned
+search) against each other.
+
+* agitated suspension, 48^3, 40 spheres D = 8 with gaps >= 0.2 and Gaussian
+  velocities: lubrication and contacts between many pairs within 80 steps;
+  FP64, both kernels, every sphere and the final fields against the oracle,
+  and the kernels bit for bit against each other;
+* the dense suspension at 96^3 with 156 spheres D = 12 (16 % solids, gaps
+  >= 1, at rest, weak gravity), 30 steps, FP64;
+* the dense suspension at its full size (384^3, 10,000 spheres, FP32
+  storage, the automatic kernel choice), where the oracle cannot run: the
+  closure of the momentum exchange in fluid at rest (Sec. 2.2, missing
+  links), the mapping of sampled spheres against a brute-force evaluation of
+  the closed-ball rule, and the two DEM kernels bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2003_01490_amd import workloads as W
+
+from harness import gpu_domain, oracle_domain, sphere_errs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _oracle_states(o, P):
+    return [o.sphere(i) for i in range(P)]
+
+
+def _check_spheres(gs, so, D, scale, tag):
+    worst = {}
+    for k, g in enumerate(gs):
+        for i, ref in enumerate(so):
+            e = sphere_errs(g.sphere(i), ref, D, scale)
+            for kk, v in e.items():
+                worst[(k, kk)] = max(worst.get((k, kk), 0.0), v)
+            assert e["x"] < TOL and e["u"] < 1e-10 and e["w"] < 1e-10, (tag, k, i, e)
+            assert e["F_tot"] < 1e-10 and e["F_fp"] < 1e-10 and e["F_col"] < 1e-10 and e["F_lub"] < 1e-10, \
+                (tag, k, i, e)
+    for k in range(len(gs)):
+        print(f"  {tag} kernel {k + 1} worst", {kk: f"{v:.1e}" for (kk2, kk), v in worst.items() if kk2 == k},
+              flush=True)
+
+
+def _same_state(a, b):
+    sa, sb = a.spheres(), b.spheres()
+    return all(np.array_equal(sa[k], sb[k]) for k in sa)
+
+
+def _compare_fields(g, o, tol=TOL):
+    cg, og = g.flags()
+    co, oo = o.flags()
+    assert np.array_equal(cg, co), "flags differ"
+    sol = co == O.SOLID
+    assert np.array_equal(og[sol], oo[sol]), "owners differ"
+    fg, fo = g.field("pdf"), o.field("pdf")
+    fs = np.abs(fo).max()
+    e = float(np.abs(fg - fo).max() / fs)
+    eu = float(np.abs(g.field("vel") - o.field("vel")).max() / fs)
+    print(f"  fields: pdf {e:.1e} vel {eu:.1e}", flush=True)
+    assert e <= tol and eu <= tol
+
+
+def test_dense_agitated_fp64_both_kernels():
+    wl = W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)
+    P = len(wl.R)
+    _case(f"agitated 48^3, {P} spheres, FP64, DEM kernels 1 and 2")
+    o = oracle_domain(wl)
+    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
+    u_scale = float(np.abs(wl.u).max())
+    F_scale = 0.0
+    contacts = lub = 0
+    done = 0
+    for chk in (5, 20, 50, 80):
+        o.step(chk - done)
+        for g in gs:
+            g.step(chk - done)
+        done = chk
+        so = _oracle_states(o, P)
+        contacts += sum(bool(np.abs(s["F_col"]).max() > 0) for s in so)
+        lub += sum(bool(np.abs(s["F_lub"]).max() > 0) for s in so)
+        u_scale = max(u_scale, max(float(np.abs(s["u"]).max()) for s in so))
+        F_scale = max(F_scale, max(max(float(np.abs(s["F_tot"]).max()), float(np.abs(s["F_fp"]).max()))
+                                   for s in so))
+        _check_spheres(gs, so, 8.0, {"u": u_scale, "F": F_scale}, f"step {chk}")
+        assert _same_state(gs[0], gs[1]), "DEM kernels differ"
+    print(f"  sphere-checkpoints in contact {contacts}, in lubrication range {lub}", flush=True)
+    assert contacts > 0 and lub > 0
+    for g in gs:
+        _compare_fields(g, o)
+
+
+def test_dense_96_fp64():
+    wl = W.dense(0, n=96, count=156)
+    P = len(wl.R)
+    _case(f"dense 96^3, {P} spheres D=12, FP64, 30 steps, DEM kernels auto and 2")
+    o = oracle_domain(wl)
+    gs = [gpu_domain(wl), gpu_domain(wl, dem_kernel=2)]
+    wgt = 4.0 / 3.0 * np.pi * 6.0 ** 3 * (wl.rho[0] - 1.0) * 2e-6
+    done = 0
+    for chk in (1, 10, 30):
+        o.step(chk - done)
+        for g in gs:
+            g.step(chk - done)
+        done = chk
+        so = _oracle_states(o, P)
+        u_scale = max(float(np.abs(s["u"]).max()) for s in so)
+        _check_spheres(gs, so, 12.0, {"u": u_scale, "F": wgt}, f"step {chk}")
+        assert _same_state(gs[0], gs[1]), "DEM kernels differ"
+    for g in gs:
+        _compare_fields(g, o)
+
+
+def _expected_codes(box_lo, box_hi, centres, R, dab, n, walls):
+    """Brute-force mapping of the cells in [box_lo, box_hi) (periodic wrap):
+    2 solid (owner = lowest id whose closed ball holds the centre), 1 shell,
+    0 fluid, 3 wall.  Squared distances as (dx dx + dy dy) + dz dz in FP64."""
+    idx = [np.arange(box_lo[a], box_hi[a]) for a in range(3)]
+    idx = [np.mod(v, n[a]) if not walls[a] else v for a, v in enumerate(idx)]
+    K, J, I = np.meshgrid(idx[2], idx[1], idx[0], indexing="ij")
+    code = np.zeros(K.shape, np.uint8)
+    owner = np.full(K.shape, -1, np.int64)
+    shell = np.zeros(K.shape, bool)
+    cc = [I + 0.5, J + 0.5, K + 0.5]
+    for j in range(len(R)):
+        d = []
+        for a in range(3):
+            v = cc[a] - centres[j, a]
+            if not walls[a]:
+                L = float(n[a])
+                v = np.where(v > 0.5 * L, v - L, np.where(v < -0.5 * L, v + L, v))
+            d.append(v)
+        d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        rs = R[j] + dab
+        inside = (d2 <= R[j] * R[j]) & (owner < 0)
+        owner[inside] = j
+        shell |= d2 <= rs * rs
+    code[shell] = 1
+    code[owner >= 0] = 2
+    wall = np.zeros(K.shape, bool)
+    for a, v in enumerate((I, J, K)):
+        if walls[a]:
+            wall |= (v == 0) | (v == n[a] - 1)
+    code[wall] = 3
+    owner[wall] = -1
+    owner[code != 2] = -1
+    return (K, J, I), code, owner
+
+
+def test_dense_full_size_properties():
+    from paper_2003_01490_amd import lbmdem as L
+
+    wl = W.dense(0, n=384, count=10000, steps=1000)
+    P = len(wl.R)
+    _case(f"dense 384^3, {P} spheres, FP32 storage, automatic DEM kernel (grid-wide)")
+    g = gpu_domain(wl, storage=L.STORE_F32)
+    g.step(1)
+    g.sync()
+    # resting fluid: the momentum exchange of every sphere closes to zero
+    s = g.spheres()
+    fmax = float(np.abs(s["F_fp"]).max())
+    tmax = float(np.abs(s["T_fp"]).max())
+    print(f"  step 1: max |F_fp| {fmax:.2e}  max |T_fp| {tmax:.2e}", flush=True)
+    assert fmax < 1e-11 and tmax < 1e-10
+    # the two DEM kernels from the same state, bit for bit
+    g1 = gpu_domain(wl, storage=L.STORE_F32, dem_kernel=1)
+    g1.step(1)
+    for k in range(3):
+        g.step(1)
+        g1.step(1)
+        assert _same_state(g, g1), f"DEM kernels differ after step {k + 2}"
+    g1.close()
+    g.step(16)
+    g.sync()
+    # mapping of sampled spheres against the closed-ball rule
+    n = (384, 384, 384)
+    walls = (0, 0, 1)
+    x = g.spheres()["x"]
+    flags = g.field("flags")
+    owner = g.field("owner")
+    rng = np.random.default_rng(5)
+    sample = rng.choice(P, 40, replace=False)
+    R = wl.R
+    # spheres whose shell ball (R + 2) can reach a cell of the box (half-edge R + 3)
+    reach = np.sqrt(3.0) * (R.max() + 3.0) + R.max() + 2.0 + 1.0
+    for i in sample:
+        lo = np.floor(x[i] - R[i] - 3).astype(int)
+        hi = np.floor(x[i] + R[i] + 3).astype(int) + 1
+        lo[2], hi[2] = max(lo[2], 0), min(hi[2], n[2])
+        dd = x - x[i]
+        for a in range(2):
+            dd[:, a] -= n[a] * np.round(dd[:, a] / n[a])
+        near = np.nonzero(np.linalg.norm(dd, axis=1) < reach)[0]  # ascending ids
+        (K, J, I), code, own = _expected_codes(lo, hi, x[near], R[near], 2.0, n, walls)
+        own = np.where(own >= 0, near[np.maximum(own, 0)], -1)
+        got = flags[K, J, I]
+        assert np.array_equal(got, code), f"flags of sphere {i} box differ"
+        sol = code == 2
+        assert np.array_equal(owner[K, J, I][sol], own[sol]), f"owners of sphere {i} box differ"
+    print(f"  mapping of {len(sample)} sampled sphere boxes bit-exact", flush=True)
+    g.close()

@@ -174,51 +174,66 @@ def test_settling_sphere_32_fp64(seed):
 
 
 def test_contact_variant_fp64():
+    """Contact and lubrication with the wall; the workgroup DEM kernel (LDS
+    variant) and the grid-wide one side by side."""
     wl = W.contact_32(0)
-    _case(f"contact_32 FP64, {wl.steps} steps")
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    _case(f"contact_32 FP64, {wl.steps} steps, DEM kernels 1 and 2")
+    o = oracle_domain(wl)
+    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
     sc = Scales(weight(wl))
     saw_contact = saw_lub = False
     done = 0
     for chk in (20, 60, 100, 150, 200, 300):
         o.step(chk - done)
-        g.step(chk - done)
+        for g in gs:
+            g.step(chk - done)
         done = chk
-        so, sg = o.sphere(0), g.sphere(0)
+        so = o.sphere(0)
         saw_contact |= bool(np.abs(so["F_col"]).max() > 0)
         saw_lub |= bool(np.abs(so["F_lub"]).max() > 0)
-        e = sphere_errs(sg, so, 2 * wl.R[0], sc.update(so))
-        print(f"  step {chk} gap {so['x'][2] - 1 - wl.R[0]:.4f}",
-              {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
-        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10 and e["F_lub"] < 1e-10, e
+        scale = sc.update(so)
+        for k, g in enumerate(gs):
+            e = sphere_errs(g.sphere(0), so, 2 * wl.R[0], scale)
+            print(f"  step {chk} kernel {k + 1} gap {so['x'][2] - 1 - wl.R[0]:.4f}",
+                  {kk: f"{v:.1e}" for kk, v in e.items()}, flush=True)
+            assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10 and e["F_lub"] < 1e-10, e
+        a, b = gs[0].sphere(0), gs[1].sphere(0)
+        assert all(np.array_equal(a[k], b[k]) for k in ("x", "u", "w", "F_tot", "T_tot")), "DEM kernels differ"
     assert saw_contact or saw_lub
-    _compare_fields(g, o)
+    for g in gs:
+        _compare_fields(g, o)
 
 
 def test_two_spheres_oblique_collision_fp64():
     n = (40, 24, 24)
-    _case("two spheres colliding, periodic")
+    _case("two spheres colliding, periodic, DEM kernels 1 and 2")
     wl = W.Workload("pair", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.02,
                                           tc=30.0, max_spheres=2),
                     np.array([[12.0, 12.1, 11.8], [12.0 + 8.45, 12.9, 12.2]]), np.array([4.0, 4.2]),
                     np.array([2.0, 3.0]), np.array([[0.04, 0.0, 0.0], [-0.04, 0.0, 0.0]]),
                     np.zeros((2, 3)), 120)
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o = oracle_domain(wl)
+    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
     done = 0
     saw = False
     sc = [Scales(), Scales()]
     for chk in (10, 30, 50, 80, 120):
         o.step(chk - done)
-        g.step(chk - done)
+        for g in gs:
+            g.step(chk - done)
         done = chk
         for i in range(2):
-            so, sg = o.sphere(i), g.sphere(i)
+            so = o.sphere(i)
             saw |= bool(np.abs(so["F_col"]).max() > 0)
-            e = sphere_errs(sg, so, 8.0, sc[i].update(so))
-            print(f"  step {chk} sphere {i}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
-            assert e["x"] < TOL and e["u"] < 1e-10 and e["w"] < 1e-10 and e["F_col"] < 1e-10, (chk, i, e)
+            scale = sc[i].update(so)
+            for k, g in enumerate(gs):
+                e = sphere_errs(g.sphere(i), so, 8.0, scale)
+                print(f"  step {chk} sphere {i} kernel {k + 1}", {kk: f"{v:.1e}" for kk, v in e.items()},
+                      flush=True)
+                assert e["x"] < TOL and e["u"] < 1e-10 and e["w"] < 1e-10 and e["F_col"] < 1e-10, (chk, i, e)
     assert saw
-    _compare_fields(g, o)
+    for g in gs:
+        _compare_fields(g, o)
 
 
 def test_prescribed_ramp_and_release():
