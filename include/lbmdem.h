@@ -100,6 +100,11 @@ typedef struct lbmdem_config {
                                (all-pairs neighbour search), 2 grid-wide
                                cooperative launch (binned neighbour search);
                                results are identical                              */
+  int32_t map_kernel;       /* boundary/commit pass: 0 automatic (one block per
+                               sphere from 128 spheres when it fits), 1 several
+                               blocks per sphere (box slabs and row chunks), 2
+                               one block per sphere (EINVAL if its LDS cube does
+                               not fit); the force sums differ in rounding order */
 } lbmdem_config;
 
 typedef struct lbmdem_domain lbmdem_domain;

@@ -28,12 +28,44 @@ int box_extent(const lbmdem_config& c) { return 2 * (int)std::ceil(c.max_radius 
 // block per sphere already does, and fewer partials keep the DEM prologue short.
 constexpr int MAP_BLOCKS_TARGET = 2048;
 
+// one-block-per-sphere boundary pass: staged cube edge (covers R + 3 around
+// the centre), surface-list capacity (cells of a ball of radius R + 1), and
+// whether it applies (auto from 128 spheres; LDS within 64 KiB; no periodic
+// axis shorter than the cube, which would stage a cell twice)
+constexpr int BALL_MIN_SPHERES = 128;
+constexpr size_t BALL_LDS_MAX = 60000;
+
+int stage_edge(const lbmdem_config& c) { return 2 * ((int)std::ceil(c.max_radius + 3.0) + 1) + 1; }
+
+int list_cap(const lbmdem_config& c) {
+  const double r = c.max_radius + 1.0;
+  return (int)std::ceil(4.0 / 3.0 * PI_H * r * r * r) + 64;
+}
+
+bool ball_possible(const lbmdem_config& c) {
+  const int he = stage_edge(c);
+  const size_t lds = (((size_t)he * he * he + 15) & ~(size_t)15) + 2 * (size_t)list_cap(c);
+  if (lds > BALL_LDS_MAX || (size_t)he * he * he > 65535) return false;
+  const int n[3] = {c.nx, c.ny, c.nz};
+  for (int a = 0; a < 3; ++a)
+    if (!c.walls[a] && n[a] < he) return false;
+  return true;
+}
+
+bool use_ball(const lbmdem_config& c) {
+  if (c.map_kernel == 1) return false;
+  if (c.map_kernel == 2) return true;
+  return c.max_spheres >= BALL_MIN_SPHERES && ball_possible(c);
+}
+
 int zblocks(const lbmdem_config& c) {
+  if (use_ball(c)) return 1;
   const int per = (MAP_BLOCKS_TARGET + std::max(c.max_spheres, 1) - 1) / std::max(c.max_spheres, 1);
   return std::max(1, std::min(std::min(c.nz, box_extent(c)), per));
 }
 
 int rowblocks(const lbmdem_config& c) {
+  if (use_ball(c)) return 1;
   const int e = std::min(c.ny, box_extent(c));
   const int full = std::max(1, (e + COMMIT_ROWS - 1) / COMMIT_ROWS);
   const long long have = (long long)std::max(c.max_spheres, 1) * zblocks(c);
@@ -142,6 +174,10 @@ const char* check_config(const lbmdem_config* c) {
   if (!(c->friction >= 0.0)) return "friction must be non-negative";
   if (!(c->cut_n > 0.0 && c->cut_tt > 0.0 && c->cut_tr > 0.0)) return "cut-offs must be positive";
   if (c->dem_kernel < 0 || c->dem_kernel > 2) return "dem_kernel must be 0..2";
+  if (c->map_kernel < 0 || c->map_kernel > 2) return "map_kernel must be 0..2";
+  if (c->map_kernel == 2 && !ball_possible(*c))
+    return "map_kernel 2 needs the staged cube (R_max + 4 cells each side) within 60000 bytes of LDS and "
+           "within every periodic extent";
   return nullptr;
 }
 
@@ -268,6 +304,7 @@ int32_t lbmdem_config_init(lbmdem_config* c) {
   c->max_spheres = 16;
   c->max_radius = 12.0;
   c->dem_kernel = 0;
+  c->map_kernel = 0;
   return LBMDEM_OK;
 }
 
@@ -369,6 +406,9 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.P = 0;
   d.ZB = zblocks(*cfg);
   d.RB = rowblocks(*cfg);
+  d.map_ball = use_ball(*cfg) ? 1 : 0;
+  d.stage_edge = stage_edge(*cfg);
+  d.list_cap = list_cap(*cfg);
   d.partial = (double*)(base + L.partial);
   d.status = (int*)(base + L.status);
   d.n_sub = cfg->n_sub;

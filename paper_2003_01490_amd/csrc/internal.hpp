@@ -110,6 +110,9 @@ struct DevDomain {
   int ZB;          // mapping blocks per sphere along z (slabs)
   int RB;          // row blocks per slab in the boundary kernel
   double* partial; // [P][ZB * RB][6]
+  int map_ball;    // boundary pass: 1 one block per sphere (k_commit_ball), 0 slab blocks
+  int stage_edge;  // edge of the LDS-staged cube of k_commit_ball (odd)
+  int list_cap;    // surface-cell list capacity of k_commit_ball
   int* status;
   // DEM parameters
   int n_sub;

@@ -480,78 +480,84 @@ __device__ inline void link_batch(const LinkCtx<T>& c, double* acc) {
   }
 }
 
+// Moving-wall bounce-back into the slots of wall cell number t (of nwall):
+// slot (y, q) receives f~_qbar(x) + 6 w_q (u_w . c_q) for the fluid cell
+// x = y + c_q.
+template <typename T>
+__device__ __forceinline__ void wall_cell_values(const DevDomain& d, T* buf, uint32_t stamp, int t, int nwall) {
+  const size_t N = (size_t)d.N;
+  if (t >= nwall) return;
+  int rem = t, ii = 0, jj = 0, kk = 0;
+  const int wz = d.walls[2], wy = d.walls[1];
+  const int nyi = d.ny - 2 * wy, nzi = d.nz - 2 * wz;
+  if (wz && rem < 2 * d.nx * d.ny) {
+    kk = rem < d.nx * d.ny ? 0 : d.nz - 1;
+    rem %= d.nx * d.ny;
+    ii = rem % d.nx;
+    jj = rem / d.nx;
+  } else {
+    if (wz) rem -= 2 * d.nx * d.ny;
+    if (wy && rem < 2 * d.nx * nzi) {
+      jj = rem < d.nx * nzi ? 0 : d.ny - 1;
+      rem %= d.nx * nzi;
+      ii = rem % d.nx;
+      kk = rem / d.nx + wz;
+    } else {
+      if (wy) rem -= 2 * d.nx * nzi;
+      ii = rem < nyi * nzi ? 0 : d.nx - 1;
+      rem %= nyi * nzi;
+      jj = rem % nyi + wy;
+      kk = rem / nyi + wz;
+    }
+  }
+  double uw[3] = {0, 0, 0};
+  if (wz && kk == 0) {
+    uw[0] = d.wall_u_lo[0];
+    uw[1] = d.wall_u_lo[1];
+    uw[2] = d.wall_u_lo[2];
+  } else if (wz && kk == d.nz - 1) {
+    uw[0] = d.wall_u_hi[0];
+    uw[1] = d.wall_u_hi[1];
+    uw[2] = d.wall_u_hi[2];
+  }
+  const long long y = cidx(d, ii, jj, kk);
+  // all neighbour states first, then the PDFs of the fluid ones, then the
+  // stores: two memory round trips per wall cell instead of one per direction
+  bool ok[Q];
+  long long xs[Q];
+  uint8_t sfl[Q];
+  unsigned long long sk[Q];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    int xi = ii + CX[q], xj = jj + CY[q], xk = kk + CZ[q];
+    ok[q] = !((d.walls[0] && (xi < 0 || xi >= d.nx)) || (d.walls[1] && (xj < 0 || xj >= d.ny)) ||
+              (d.walls[2] && (xk < 0 || xk >= d.nz)));
+    xs[q] = cidx(d, wrapi(xi, d.nx), wrapi(xj, d.ny), wrapi(xk, d.nz));
+    if (ok[q]) {
+      sfl[q] = d.flags[xs[q]];
+      sk[q] = d.claim[xs[q]];
+    }
+  }
+  double v[Q];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    // fluid after this update: not a wall, not claimed by this stamp
+    ok[q] = ok[q] && !(sfl[q] & F_WALL) && (uint32_t)(sk[q] >> 32) != stamp;
+    if (ok[q]) v[q] = ldv<T>(buf + (size_t)OPP[q] * N + xs[q]);
+  }
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+    if (ok[q])
+      stv<T>(buf + (size_t)q * N + y, v[q] + 6.0 * WQ[q] * (uw[0] * CX[q] + uw[1] * CY[q] + uw[2] * CZ[q]));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t stamp, int nwall) {
   const int nsb = d.P * d.ZB * d.RB;
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
   if ((int)blockIdx.x >= nsb) {
-    // moving-wall bounce-back into wall-cell slots: slot (y, q) receives
-    // f~_qbar(x) + 6 w_q (u_w . c_q) for the fluid cell x = y + c_q
-    const int t = (blockIdx.x - nsb) * blockDim.x + threadIdx.x;
-    if (t >= nwall) return;
-    int rem = t, ii = 0, jj = 0, kk = 0;
-    const int wz = d.walls[2], wy = d.walls[1];
-    const int nyi = d.ny - 2 * wy, nzi = d.nz - 2 * wz;
-    if (wz && rem < 2 * d.nx * d.ny) {
-      kk = rem < d.nx * d.ny ? 0 : d.nz - 1;
-      rem %= d.nx * d.ny;
-      ii = rem % d.nx;
-      jj = rem / d.nx;
-    } else {
-      if (wz) rem -= 2 * d.nx * d.ny;
-      if (wy && rem < 2 * d.nx * nzi) {
-        jj = rem < d.nx * nzi ? 0 : d.ny - 1;
-        rem %= d.nx * nzi;
-        ii = rem % d.nx;
-        kk = rem / d.nx + wz;
-      } else {
-        if (wy) rem -= 2 * d.nx * nzi;
-        ii = rem < nyi * nzi ? 0 : d.nx - 1;
-        rem %= nyi * nzi;
-        jj = rem % nyi + wy;
-        kk = rem / nyi + wz;
-      }
-    }
-    double uw[3] = {0, 0, 0};
-    if (wz && kk == 0) {
-      uw[0] = d.wall_u_lo[0];
-      uw[1] = d.wall_u_lo[1];
-      uw[2] = d.wall_u_lo[2];
-    } else if (wz && kk == d.nz - 1) {
-      uw[0] = d.wall_u_hi[0];
-      uw[1] = d.wall_u_hi[1];
-      uw[2] = d.wall_u_hi[2];
-    }
-    const long long y = cidx(d, ii, jj, kk);
-    // all neighbour states first, then the PDFs of the fluid ones, then the
-    // stores: two memory round trips per wall cell instead of one per direction
-    bool ok[Q];
-    long long xs[Q];
-    uint8_t sfl[Q];
-    unsigned long long sk[Q];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      int xi = ii + CX[q], xj = jj + CY[q], xk = kk + CZ[q];
-      ok[q] = !((d.walls[0] && (xi < 0 || xi >= d.nx)) || (d.walls[1] && (xj < 0 || xj >= d.ny)) ||
-                (d.walls[2] && (xk < 0 || xk >= d.nz)));
-      xs[q] = cidx(d, wrapi(xi, d.nx), wrapi(xj, d.ny), wrapi(xk, d.nz));
-      if (ok[q]) {
-        sfl[q] = d.flags[xs[q]];
-        sk[q] = d.claim[xs[q]];
-      }
-    }
-    double v[Q];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      // fluid after this update: not a wall, not claimed by this stamp
-      ok[q] = ok[q] && !(sfl[q] & F_WALL) && (uint32_t)(sk[q] >> 32) != stamp;
-      if (ok[q]) v[q] = ldv<T>(buf + (size_t)OPP[q] * N + xs[q]);
-    }
-#pragma unroll
-    for (int q = 1; q < Q; ++q)
-      if (ok[q])
-        stv<T>(buf + (size_t)q * N + y, v[q] + 6.0 * WQ[q] * (uw[0] * CX[q] + uw[1] * CY[q] + uw[2] * CZ[q]));
+    wall_cell_values<T>(d, buf, stamp, (blockIdx.x - nsb) * blockDim.x + threadIdx.x, nwall);
     return;
   }
   const int nbs = d.ZB * d.RB;
@@ -669,6 +675,194 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t s
   }
 }
 
+// Many spheres: one block per sphere.  The states of all cells within R + 3 of
+// the new centre (every cell a link of the sphere or its CLI neighbour can
+// touch) are staged in LDS in one pass with many loads in flight; then the
+// flags of the cells in the old and new shell balls are committed, the
+// sphere's solid cells that have a non-own neighbour are listed, and their
+// links are formed as in k_commit.  Dynamic LDS: edge^3 state bytes plus the
+// surface list.
+constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int cur, uint32_t stamp, int nwall) {
+  T* buf = (T*)d.pdf[cur];
+  const size_t N = (size_t)d.N;
+  const int P = d.P;
+  if ((int)blockIdx.x >= P) {
+    wall_cell_values<T>(d, buf, stamp, (blockIdx.x - P) * blockDim.x + threadIdx.x, nwall);
+    return;
+  }
+  extern __shared__ uint8_t smem[];
+  const int he = d.stage_edge, H = he / 2;
+  const int NS = he * he * he;
+  uint8_t* st = smem;
+  uint16_t* list = reinterpret_cast<uint16_t*>(smem + ((NS + 15) & ~15));
+  __shared__ double red[6][4];
+  const int i = blockIdx.x;
+  const double xp[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
+  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
+  const double up[3] = {d.p.u[3 * i], d.p.u[3 * i + 1], d.p.u[3 * i + 2]};
+  const double wp[3] = {d.p.w[3 * i], d.p.w[3 * i + 1], d.p.w[3 * i + 2]};
+  const double R = d.p.R[i];
+  double rs2, rl2;
+  {
+#pragma clang fp contract(off)
+    const double rs = R + d.delta_ab, rl = R + 3.0;
+    rs2 = rs * rs;
+    rl2 = rl * rl;
+  }
+  const int n[3] = {d.nx, d.ny, d.nz};
+  bool finite = isfinite(xp[0]) && isfinite(xp[1]) && isfinite(xp[2]);
+  int lo[3];
+  for (int a = 0; a < 3; ++a) lo[a] = finite ? (int)floor(xp[a]) - H : 0;
+
+  // 1. stage: eight cells per thread and pass, all loads issued before use
+  for (int t0 = threadIdx.x; t0 < NS; t0 += 8 * blockDim.x) {
+    long long cc[8];
+    uint8_t code[8], fl[8];
+    unsigned long long kc[8];
+    uint32_t ss[8];
+    bool ld[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * blockDim.x;
+      ld[u] = false;
+      code[u] = L_UNSET;
+      if (t < NS && finite) {
+        const int g[3] = {lo[0] + t % he, lo[1] + (t / he) % he, lo[2] + t / (he * he)};
+        bool out = false;
+        int ijk[3];
+        for (int a = 0; a < 3; ++a) {
+          if (d.walls[a]) {
+            out = out || g[a] < 0 || g[a] >= n[a];
+            ijk[a] = g[a];
+          } else {
+            ijk[a] = wrapmod(g[a], n[a]);
+          }
+        }
+        if (out) {
+          code[u] = L_WALL;
+        } else if (cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rl2) {
+          cc[u] = cidx(d, ijk[0], ijk[1], ijk[2]);
+          ld[u] = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ld[u]) {
+        fl[u] = d.flags[cc[u]];
+        kc[u] = d.claim[cc[u]];
+        ss[u] = d.shellstamp[cc[u]];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * blockDim.x;
+      if (t >= NS) continue;
+      if (ld[u]) {
+        if (fl[u] & F_WALL) {
+          code[u] = L_WALL;
+        } else if ((uint32_t)(kc[u] >> 32) == stamp) {
+          code[u] = (int)(0xFFFFFFFFu - (uint32_t)(kc[u] & 0xFFFFFFFFull)) == i ? L_OWN : L_OTHER;
+        } else {
+          code[u] = ss[u] == stamp ? L_SHELL : L_FLUID;
+        }
+      }
+      st[t] = code[u];
+    }
+  }
+  __syncthreads();
+
+  // 2. flags and owners of the cells in the old and new shell balls; a cell
+  // claimed by another sphere is committed by that sphere's block
+  Box bx;
+  sphere_box(d, i, true, bx);
+  const int nbox = bx.ext[0] * bx.ext[1] * bx.ext[2];
+  for (int t = threadIdx.x; t < nbox; t += blockDim.x) {
+    const int tx = t % bx.ext[0], ty = (t / bx.ext[0]) % bx.ext[1], tz = t / (bx.ext[0] * bx.ext[1]);
+    const int g[3] = {bx.lo[0] + tx, bx.lo[1] + ty, bx.lo[2] + tz};
+    int ijk[3], h[3];
+    bool in = true;
+    for (int a = 0; a < 3; ++a) {
+      ijk[a] = d.walls[a] ? g[a] : wrapmod(g[a], n[a]);
+      h[a] = d.walls[a] ? g[a] - lo[a] : wrapmod(g[a] - lo[a], n[a]);
+      in = in && h[a] >= 0 && h[a] < he;
+    }
+    if (!(cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) && !(cell_d2(d, ijk[0], ijk[1], ijk[2], xo) <= rs2))
+      continue;
+    const long long c = cidx(d, ijk[0], ijk[1], ijk[2]);
+    const uint8_t sc = in ? st[h[0] + he * (h[1] + he * h[2])] : L_UNSET;
+    if (sc == L_WALL || sc == L_OTHER) continue;
+    if (sc == L_OWN) {
+      d.flags[c] = F_SOLID;
+      d.owner[c] = i;
+    } else if (sc == L_SHELL || sc == L_FLUID) {
+      d.flags[c] = sc == L_SHELL ? F_SHELL : (uint8_t)0;
+    } else {
+      int own = -1;
+      const int ns = new_state(d, c, stamp, &own);
+      if (ns == S_WALL) continue;
+      d.flags[c] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
+      if (ns == S_SOLID) d.owner[c] = own;
+    }
+  }
+
+  // 3. solid cells of this sphere with a neighbour that is not, listed in
+  // cube order (ordered compaction: wavefront ballots and per-wave offsets),
+  // so that every cell is summed by the same thread on every run
+  __shared__ int wcount[4];
+  int base = 0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int t0 = 0; t0 < NS; t0 += blockDim.x) {
+    const int t = t0 + threadIdx.x;
+    bool surf = false;
+    if (t < NS && st[t] == L_OWN) {
+#pragma unroll
+      for (int q = 1; q < Q; ++q) surf = surf || st[t + CX[q] + he * (CY[q] + he * CZ[q])] != L_OWN;
+    }
+    const unsigned long long m = __ballot(surf);
+    if (lane == 0) wcount[wid] = __popcll(m);
+    __syncthreads();
+    int off = base, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wid) off += wcount[w];
+      tot += wcount[w];
+    }
+    if (surf) list[off + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)t;
+    base += tot;
+    __syncthreads();
+  }
+
+  // 4. links of the listed cells
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int nl = base;  // the same in every thread
+  for (int e = threadIdx.x; e < nl; e += blockDim.x) {
+    const int t = list[e];
+    const int hx = t % he, hy = (t / he) % he, hz = t / (he * he);
+    const int ii = d.walls[0] ? lo[0] + hx : wrapmod(lo[0] + hx, n[0]);
+    const int jj = d.walls[1] ? lo[1] + hy : wrapmod(lo[1] + hy, n[1]);
+    const int kk = d.walls[2] ? lo[2] + hz : wrapmod(lo[2] + hz, n[2]);
+    const long long yc = cidx(d, ii, jj, kk);
+    const LinkCtx<T> lc{d, buf, N, st, true, t, he, he, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
+    link_batch<T, 1>(lc, acc);
+    link_batch<T, 7>(lc, acc);
+    link_batch<T, 13>(lc, acc);
+  }
+  // 5. fixed-order block reduction
+  for (int k = 0; k < 6; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[k][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = 0.0;
+    for (int w4 = 0; w4 < (int)(blockDim.x >> 6); ++w4) v += red[threadIdx.x][w4];
+    d.partial[(size_t)i * 6 + threadIdx.x] = v;
+  }
+}
+
 static int wall_cell_count(const DevDomain& d) {
   int n = 0;
   const int nzi = d.nz - 2 * d.walls[2], nyi = d.ny - 2 * d.walls[1];
@@ -688,9 +882,16 @@ static void launch_update_t(const DevDomain& d, int cur, uint32_t stamp, bool re
                             hipStream_t s) {
   const int nsb = d.P * d.ZB;
   if (nsb > 0 && reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, cur, stamp);
-  const int ncb = nsb * d.RB;
   const int nwall = wall_cell_count(d);
   const int wblocks = (nwall + 255) / 256;
+  if (d.map_ball) {
+    const size_t lds = (((size_t)d.stage_edge * d.stage_edge * d.stage_edge + 15) & ~(size_t)15) +
+                       2 * (size_t)d.list_cap;
+    if (d.P + wblocks > 0)
+      hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P + wblocks), dim3(256), lds, s, d, cur, stamp, nwall);
+    return;
+  }
+  const int ncb = nsb * d.RB;
   if (ncb + wblocks > 0)
     hipLaunchKernelGGL(k_commit<T>, dim3(ncb + wblocks), dim3(256), 0, s, d, cur, stamp, nwall);
 }

@@ -48,6 +48,7 @@ class Config(C.Structure):
         ("lub_mask", C.c_int32), ("max_spheres", C.c_int32),
         ("max_radius", C.c_double),
         ("dem_kernel", C.c_int32),
+        ("map_kernel", C.c_int32),
     ]
 
 

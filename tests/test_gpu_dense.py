@@ -1,6 +1,7 @@
-"""Many spheres: the GPU path against the FP64 oracle, and the two DEM kernels
-(one workgroup with an all-pairs neighbour search; grid-wide with binned
-search) against each other.
+"""Many spheres: the GPU path against the FP64 oracle, the two DEM kernels (one
+workgroup with an all-pairs neighbour search; grid-wide with binned search)
+against each other, and both boundary passes (several blocks per sphere; one
+block per sphere with its cells staged in LDS) against the oracle.
 
 * agitated suspension, 48^3, 40 spheres D = 8 with gaps >= 0.2 and Gaussian
   velocities: lubrication and contacts between many pairs within 80 steps;
@@ -46,7 +47,7 @@ def _check_spheres(gs, so, D, scale, tag):
             assert e["F_tot"] < 1e-10 and e["F_fp"] < 1e-10 and e["F_col"] < 1e-10 and e["F_lub"] < 1e-10, \
                 (tag, k, i, e)
     for k in range(len(gs)):
-        print(f"  {tag} kernel {k + 1} worst", {kk: f"{v:.1e}" for (kk2, kk), v in worst.items() if kk2 == k},
+        print(f"  {tag} domain {k} worst", {kk: f"{v:.1e}" for (kk2, kk), v in worst.items() if kk2 == k},
               flush=True)
 
 
@@ -72,9 +73,10 @@ def _compare_fields(g, o, tol=TOL):
 def test_dense_agitated_fp64_both_kernels():
     wl = W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)
     P = len(wl.R)
-    _case(f"agitated 48^3, {P} spheres, FP64, DEM kernels 1 and 2")
+    _case(f"agitated 48^3, {P} spheres, FP64, (DEM, map) kernels (1,1) (2,1) (2,2)")
     o = oracle_domain(wl)
-    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
+    gs = [gpu_domain(wl, dem_kernel=1, map_kernel=1), gpu_domain(wl, dem_kernel=2, map_kernel=1),
+          gpu_domain(wl, dem_kernel=2, map_kernel=2)]
     u_scale = float(np.abs(wl.u).max())
     F_scale = 0.0
     contacts = lub = 0
@@ -101,9 +103,9 @@ def test_dense_agitated_fp64_both_kernels():
 def test_dense_96_fp64():
     wl = W.dense(0, n=96, count=156)
     P = len(wl.R)
-    _case(f"dense 96^3, {P} spheres D=12, FP64, 30 steps, DEM kernels auto and 2")
+    _case(f"dense 96^3, {P} spheres D=12, FP64, 30 steps, (DEM, map) kernels auto, (2, auto), (1, 1)")
     o = oracle_domain(wl)
-    gs = [gpu_domain(wl), gpu_domain(wl, dem_kernel=2)]
+    gs = [gpu_domain(wl), gpu_domain(wl, dem_kernel=2), gpu_domain(wl, dem_kernel=1, map_kernel=1)]
     wgt = 4.0 / 3.0 * np.pi * 6.0 ** 3 * (wl.rho[0] - 1.0) * 2e-6
     done = 0
     for chk in (1, 10, 30):
