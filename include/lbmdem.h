@@ -189,6 +189,19 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
  * values of the next step. */
 int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f);
 
+/* Bitwise checkpoint of a domain (Sec. 2 state: the current PDFs with the
+ * boundary values of the next step, cell flags and owners, particle state,
+ * contact histories, averaging memory and step count) into a host buffer.
+ * With host_blob == NULL, *bytes receives the size needed; otherwise *bytes is
+ * the buffer size on entry and the size written on return (LBMDEM_EINVAL and
+ * the size needed if it is too small).  Synchronises the domain's stream. */
+int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes);
+
+/* Restores a checkpoint written by lbmdem_save into a domain created with an
+ * equal configuration (LBMDEM_EINVAL otherwise); continuing from it gives
+ * results bit for bit equal to continuing the saved domain. */
+int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes);
+
 /* Kernel timing with HIP events on the domain's stream (for roofline
  * reports).  enable: 0 off, 1 the sweep only (each event record adds a small
  * gap to the queue, so level 1 disturbs the step least), 2 every kernel group.

@@ -784,6 +784,134 @@ int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
   return remap(dom, false);
 }
 
+// ---- checkpoint ------------------------------------------------------------
+
+namespace {
+
+constexpr char CK_MAGIC[8] = {'L', 'B', 'M', 'D', 'E', 'M', 'C', 'K'};
+constexpr uint32_t CK_VERSION = 1;
+
+struct CkHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t cfg_bytes;
+  lbmdem_config cfg;
+  int64_t steps;
+  uint32_t stamp;
+  int32_t cur;
+  uint64_t bar_base;
+  int32_t P;
+  int32_t pad;
+  uint64_t seg[3];  // bytes of: current PDF buffer, cell arrays, particle block
+};
+
+bool same_config(const lbmdem_config& a, const lbmdem_config& b) {
+  bool eq = a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.collision == b.collision &&
+            a.boundary == b.boundary && a.storage == b.storage && a.n_sub == b.n_sub &&
+            a.force_averaging == b.force_averaging && a.lub_mask == b.lub_mask &&
+            a.max_spheres == b.max_spheres && a.dem_kernel == b.dem_kernel && a.map_kernel == b.map_kernel;
+  for (int k = 0; k < 3; ++k)
+    eq = eq && a.walls[k] == b.walls[k] && a.wall_u_lo[k] == b.wall_u_lo[k] && a.wall_u_hi[k] == b.wall_u_hi[k] &&
+         a.gravity[k] == b.gravity[k];
+  eq = eq && a.nu == b.nu && a.magic_lambda == b.magic_lambda && a.lambda_b == b.lambda_b &&
+       a.delta_ab == b.delta_ab && a.e_dry == b.e_dry && a.poisson_ratio == b.poisson_ratio &&
+       a.friction == b.friction && a.tc == b.tc && a.dmin == b.dmin && a.cut_n == b.cut_n &&
+       a.cut_tt == b.cut_tt && a.cut_tr == b.cut_tr && a.max_radius == b.max_radius;
+  return eq;
+}
+
+// device segments of a checkpoint: the current PDF buffer, the cell arrays
+// (flags, owner, claims, shell stamps) and the particle block
+void ck_segments(const lbmdem_domain* dom, char** at, size_t* len) {
+  char* base = (char*)dom->region;
+  const Layout& L = dom->L;
+  at[0] = base + (dom->cur ? L.pdf1 : L.pdf0);
+  len[0] = L.pdf1 - L.pdf0;
+  at[1] = base + L.flags;
+  len[1] = L.stage - L.flags;
+  at[2] = base + L.x;
+  len[2] = L.total - L.x;
+}
+
+}  // namespace
+
+int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes) {
+  if (!dom || !bytes) return LBMDEM_EINVAL;
+  char* at[3];
+  size_t len[3];
+  ck_segments(dom, at, len);
+  const size_t P = dom->hR.size();
+  const size_t need = sizeof(CkHeader) + 8 * P + len[0] + len[1] + len[2];
+  if (!host_blob) {
+    *bytes = need;
+    return LBMDEM_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(dom, LBMDEM_EINVAL, "checkpoint buffer too small");
+  }
+  CkHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, CK_MAGIC, 8);
+  h.version = CK_VERSION;
+  h.cfg_bytes = sizeof(lbmdem_config);
+  h.cfg = dom->cfg;
+  h.steps = dom->steps;
+  h.stamp = dom->stamp;
+  h.cur = dom->cur;
+  h.bar_base = dom->bar_base;
+  h.P = (int32_t)P;
+  for (int k = 0; k < 3; ++k) h.seg[k] = len[k];
+  char* out = (char*)host_blob;
+  std::memcpy(out, &h, sizeof(h));
+  out += sizeof(h);
+  if (P) std::memcpy(out, dom->hR.data(), 8 * P);
+  out += 8 * P;
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(dom, hipMemcpyAsync(out, at[k], len[k], hipMemcpyDeviceToHost, dom->stream));
+    out += len[k];
+  }
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  *bytes = need;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes) {
+  if (!dom || !host_blob) return LBMDEM_EINVAL;
+  CkHeader h;
+  if (bytes < sizeof(h)) return fail(dom, LBMDEM_EINVAL, "checkpoint truncated");
+  std::memcpy(&h, host_blob, sizeof(h));
+  if (std::memcmp(h.magic, CK_MAGIC, 8) != 0 || h.version != CK_VERSION || h.cfg_bytes != sizeof(lbmdem_config))
+    return fail(dom, LBMDEM_EINVAL, "not a checkpoint of this library version");
+  if (!same_config(h.cfg, dom->cfg)) return fail(dom, LBMDEM_EINVAL, "checkpoint of a different configuration");
+  if (h.P < 0 || h.P > dom->cfg.max_spheres || (h.cur != 0 && h.cur != 1))
+    return fail(dom, LBMDEM_EINVAL, "corrupt checkpoint header");
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  harvest(dom);
+  dom->cur = h.cur;
+  char* at[3];
+  size_t len[3];
+  ck_segments(dom, at, len);
+  const size_t need = sizeof(CkHeader) + 8 * (size_t)h.P + len[0] + len[1] + len[2];
+  if (bytes < need || h.seg[0] != len[0] || h.seg[1] != len[1] || h.seg[2] != len[2])
+    return fail(dom, LBMDEM_EINVAL, "checkpoint size does not match this domain");
+  const char* in = (const char*)host_blob + sizeof(h);
+  dom->hR.assign((const double*)in, (const double*)in + h.P);
+  in += 8 * (size_t)h.P;
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(dom, hipMemcpyAsync(at[k], in, len[k], hipMemcpyHostToDevice, dom->stream));
+    in += len[k];
+  }
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  dom->steps = h.steps;
+  dom->stamp = h.stamp;
+  dom->bar_base = h.bar_base;
+  dom->d.P = h.P;
+  dom->failed = 0;
+  return LBMDEM_OK;
+}
+
 int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable) {
   if (!dom) return LBMDEM_EINVAL;
   HIPCHK(dom, hipStreamSynchronize(dom->stream));

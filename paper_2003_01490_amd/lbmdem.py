@@ -85,6 +85,8 @@ def lib():
         "lbmdem_get_spheres": (C.c_int32, [vp, C.c_int32, ip, dp, dp, dp, dp, dp, dp, dp]),
         "lbmdem_get_field": (C.c_int32, [vp, C.c_int32, vp, C.c_size_t, C.c_int32]),
         "lbmdem_set_pdf": (C.c_int32, [vp, dp]),
+        "lbmdem_save": (C.c_int32, [vp, vp, C.POINTER(C.c_size_t)]),
+        "lbmdem_restore": (C.c_int32, [vp, vp, C.c_size_t]),
         "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
         "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
         "lbmdem_sweep_bytes": (C.c_double, [vp]),
@@ -239,6 +241,18 @@ class Domain:
         out = {k: np.zeros((n, 3)) for k in keys}
         self._check(lib().lbmdem_get_spheres(self.h, n, idp, *[_dp(out[k]) for k in keys]))
         return out
+
+    # --- checkpoint ---------------------------------------------------------
+    def save(self) -> bytes:
+        """Bitwise checkpoint (host bytes)."""
+        n = C.c_size_t(0)
+        self._check(lib().lbmdem_save(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().lbmdem_save(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def restore(self, blob: bytes):
+        self._check(lib().lbmdem_restore(self.h, blob, len(blob)))
 
     # --- time stepping ----------------------------------------------------
     def step(self, n=1):
