@@ -107,6 +107,144 @@ def cpu_baseline(wl, steps):
     return n * steps / dt / 1e6, dt
 
 
+def serve_bench(args):
+    """Serving stream: independent sphere-wall requests with Poisson arrivals,
+    each run until its sphere rebounds (first apex after the wall contact) or a
+    step cap, FP32 storage.  Continuous batching: arrived requests are admitted
+    while their footprints fit the pool budget, all admitted domains advance
+    together in chunks of steps, stopped ones are retired at once.  Baseline:
+    the same requests one at a time in arrival order (each domain stepped alone).
+    """
+    import numpy as np
+    import torch
+
+    from paper_2003_01490_amd import lbmdem as L
+    from paper_2003_01490_amd import workloads as W
+
+    reqs = W.serve_requests(args.seed, args.requests, rate=args.rate)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    pool = int(args.pool_gb * 2 ** 30)
+    bytes_per_cell = 2 * 19 * 4 + 1
+
+    def make(req):
+        wl = W.serve_workload(req)
+        cfg = _gpu_params(wl, L.STORE_F32)
+        dom = L.Domain(cfg, device=dev, stream=stream)
+        dom.add_spheres(wl.x, wl.R, wl.rho)
+        r = wl.ramp
+        dom.set_mode(0, L.PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
+        dom.set_stop_rule(L.STOP_REBOUND, args.max_steps)
+        return dom
+
+    def footprint(req):
+        return L.footprint_bytes(_gpu_params(W.serve_workload(req), L.STORE_F32))
+
+    def summary(done, wall, busy_ms):
+        lat = np.array([d["latency"] for d in done])
+        cells = sum(d["cells"] * d["steps"] for d in done)
+        return {"solves_per_s": round(len(done) / wall, 4), "wall_s": round(wall, 3),
+                "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+                "gpu_busy": round(busy_ms / 1e3 / wall, 4),
+                "aggregate_GBps": round(cells * bytes_per_cell / wall / 1e9, 1),
+                "aggregate_MLUPS": round(cells / wall / 1e6, 1),
+                "rebounds": sum(d["stopped_by_rule"] for d in done)}
+
+    # --- continuous batching
+    batch = L.Batch(stream, pool)
+    pending = sorted(reqs, key=lambda r: r["arrival"])
+    active, done, used = {}, [], 0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    busy = 0.0
+    t0 = time.perf_counter()
+    while pending or active:
+        now = time.perf_counter() - t0
+        while pending and pending[0]["arrival"] <= now:
+            fp = footprint(pending[0])
+            if used + fp > pool and active:
+                break
+            req = pending.pop(0)
+            dom = make(req)
+            slot = batch.admit(dom)
+            active[slot] = (req, dom, fp)
+            used += fp
+        if not active:
+            time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
+            continue
+        ev0.record(stream)
+        batch.step(args.chunk)
+        ev1.record(stream)
+        fin = batch.done()
+        busy += ev0.elapsed_time(ev1)
+        st = batch.status()
+        for slot in fin:
+            req, dom, fp = active.pop(slot)
+            steps = st[slot][0]
+            batch.retire(slot)
+            done.append(dict(id=req["id"], latency=time.perf_counter() - t0 - req["arrival"], steps=steps,
+                             cells=dom.N, stopped_by_rule=steps < args.max_steps))
+            dom.close()
+            used -= fp
+        print(f"[serve] t {time.perf_counter() - t0:7.2f}s active {len(active):3d} done {len(done):3d} "
+              f"pending {len(pending):3d}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    batch.close()
+    res = summary(done, wall, busy)
+
+    base = None
+    if args.serve_baseline:
+        done_b = []
+        busy_b = 0.0
+        t0 = time.perf_counter()
+        for req in sorted(reqs, key=lambda r: r["arrival"]):
+            now = time.perf_counter() - t0
+            if req["arrival"] > now:
+                time.sleep(req["arrival"] - now)
+            dom = make(req)
+            while True:
+                ev0.record(stream)
+                dom.step(args.chunk)
+                ev1.record(stream)
+                steps, stopped = dom.progress()
+                busy_b += ev0.elapsed_time(ev1)
+                if stopped:
+                    break
+            done_b.append(dict(id=req["id"], latency=time.perf_counter() - t0 - req["arrival"], steps=steps,
+                               cells=dom.N, stopped_by_rule=steps < args.max_steps))
+            dom.close()
+            print(f"[serve-fifo] t {time.perf_counter() - t0:7.2f}s done {len(done_b):3d}", file=sys.stderr,
+                  flush=True)
+        base = summary(done_b, time.perf_counter() - t0, busy_b)
+
+    cells = np.array([np.prod(r["L"]) for r in reqs])
+    St = np.array([r["St"] for r in reqs])
+    result = {
+        "metric": METRIC,
+        "value": res["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": int(sum(d["steps"] for d in done)),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream: {args.requests} sphere-wall requests, Poisson arrivals "
+                               f"{args.rate}/s, edges U{{48..192}}, D U[6,24], St logU[1,1000] "
+                               f"(median {np.median(St):.1f}), rho_r U[1.5,8], u_s 0.02, stop at rebound "
+                               f"or {args.max_steps} steps, FP32 storage",
+                   "pool_GiB": args.pool_gb, "chunk_steps": args.chunk, "seed": args.seed,
+                   "mean_cells": int(cells.mean()), "parallelism": "single GPU"},
+        "batched": res,
+        "fifo_one_at_a_time": base,
+    }
+    if base:
+        result["speedup_vs_fifo"] = round(res["solves_per_s"] / base["solves_per_s"], 3)
+    print(json.dumps(result))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +255,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=64, help="serving stream: number of requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving stream: arrivals per second")
+    ap.add_argument("--pool-gb", type=float, default=48.0, help="serving stream: pool budget (GiB)")
+    ap.add_argument("--max-steps", type=int, default=6000, help="serving stream: step cap per request")
+    ap.add_argument("--chunk", type=int, default=100, help="serving stream: steps per batch call")
+    ap.add_argument("--serve-baseline", action="store_true", help="serving stream: also run FIFO one at a time")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -124,6 +268,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)
+    if args.workload == "serve":
+        serve_bench(args)
+        return
 
     import torch
 

@@ -61,6 +61,7 @@ enum { LBMDEM_TRT_AB = 0, LBMDEM_TRT_B = 1, LBMDEM_TRT = 2, LBMDEM_SRT = 3 };
 enum { LBMDEM_BC_CLI = 0, LBMDEM_BC_BOUNCE_BACK = 1 };
 enum { LBMDEM_STORE_F64 = 0, LBMDEM_STORE_F32 = 1, LBMDEM_STORE_F16 = 2 };
 enum { LBMDEM_FREE = 0, LBMDEM_PRESCRIBED = 1, LBMDEM_FIXED = 2 };
+enum { LBMDEM_STOP_NONE = 0, LBMDEM_STOP_REBOUND = 1 };
 enum {
   LBMDEM_FIELD_RHO = 0,   /* double[N]                                      */
   LBMDEM_FIELD_VEL = 1,   /* double[3N], component-major                    */
@@ -201,6 +202,52 @@ int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes);
  * equal configuration (LBMDEM_EINVAL otherwise); continuing from it gives
  * results bit for bit equal to continuing the saved domain. */
 int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes);
+
+/* Stop rule of a domain, evaluated on the device at the end of every step:
+ * LBMDEM_STOP_NONE, or LBMDEM_STOP_REBOUND (sphere 0: first apex after its
+ * first contact has ended, i.e. u_z turns from positive to non-positive, the
+ * rebound of Sec. 4.4); and/or a step limit (max_steps <= 0: none).  A domain
+ * that meets it is frozen at the start of the next step: its state stays that
+ * of the step that met the rule, and further steps do nothing.  Setting a rule
+ * clears a previous stop. */
+int32_t lbmdem_set_stop_rule(lbmdem_domain* dom, int32_t rule, int64_t max_steps);
+
+/* Synchronising read of the step count and whether the domain has stopped. */
+int32_t lbmdem_get_progress(lbmdem_domain* dom, int64_t* steps, int32_t* stopped);
+
+/* ---- batches: many domains advanced together (continuous batching) -------
+ * A batch steps all its admitted domains with one launch per kernel kind
+ * (fused stream-collide, DEM sub-cycles, claims, reconstruction, boundary
+ * pass), replayed from a captured HIP graph.  Domains keep their state in
+ * their own regions; admission checks lbmdem_footprint_bytes() against the
+ * batch's pool budget; a domain that meets its stop rule freezes without
+ * affecting the others and can be retired and replaced between steps.
+ * Domains must be created on the batch's stream, share one storage precision,
+ * and use the slab boundary pass (map_kernel 1, or automatic below 128
+ * spheres); a domain in a batch is stepped only through it. */
+typedef struct lbmdem_batch lbmdem_batch;
+
+/* hip_stream: the stream all batched work is enqueued on; pool_bytes: budget
+ * for the summed footprints of the admitted domains. */
+int32_t lbmdem_batch_create(void* hip_stream, size_t pool_bytes, lbmdem_batch** out);
+int32_t lbmdem_batch_destroy(lbmdem_batch* batch);
+/* 1 (default): replay one captured step graph; 0: launch directly. */
+int32_t lbmdem_batch_set_graph(lbmdem_batch* batch, int32_t use_graph);
+/* Admits a domain; *slot receives its id within the batch.  LBMDEM_ENOMEM if
+ * the pool budget would be exceeded (admit it later). */
+int32_t lbmdem_batch_admit(lbmdem_batch* batch, lbmdem_domain* dom, int32_t* slot);
+/* Removes a domain (its state is kept; it may be read or stepped alone). */
+int32_t lbmdem_batch_retire(lbmdem_batch* batch, lbmdem_domain* dom);
+/* Enqueues nsteps steps of every admitted domain that has not stopped. */
+int32_t lbmdem_batch_step(lbmdem_batch* batch, int32_t nsteps);
+/* Synchronising: slots, step counts and stop flags of the admitted domains
+ * (any array may be NULL); *n is the capacity on entry, the count on return. */
+int32_t lbmdem_batch_status(lbmdem_batch* batch, int32_t* slots, int64_t* steps, int32_t* stopped,
+                            int32_t* n);
+/* Synchronising: slots of the admitted domains that have stopped; *n is the
+ * capacity of slots on entry and the count on return. */
+int32_t lbmdem_batch_done(lbmdem_batch* batch, int32_t* slots, int32_t* n);
+const char* lbmdem_batch_last_error(const lbmdem_batch* batch);
 
 /* Kernel timing with HIP events on the domain's stream (for roofline
  * reports).  enable: 0 off, 1 the sweep only (each event record adds a small

@@ -32,6 +32,10 @@ def build(verbose: bool = False) -> str:
         hipcc(), f"--offload-arch={OFFLOAD_ARCH}", "-O3", "-std=c++17", "-fPIC",
         # packed FP32 instructions are kept out of generated code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # a*b+c is fused only within one source expression, so a device
+        # function rounds the same way in every kernel it is inlined into
+        # (a domain stepped alone or in a batch gives identical bits)
+        "-ffp-contract=on",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         "-Wno-unused-result",
     ]

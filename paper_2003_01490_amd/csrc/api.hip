@@ -96,7 +96,7 @@ void bin_dims(const lbmdem_config& c, int* nb) {
 struct Layout {
   size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
-      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, barrier, partial, status;
+      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, barrier, ctl, partial, status;
   size_t total;
 };
 
@@ -148,6 +148,7 @@ Layout make_layout(const lbmdem_config& c) {
   bin_dims(c, nb);
   L.bins = take(4 * (size_t)nb[0] * nb[1] * nb[2] * (1 + BIN_CAP));
   L.barrier = take(256);
+  L.ctl = take(sizeof(DevCtl));
   L.partial = take(48 * P * (size_t)zblocks(c) * (size_t)rowblocks(c));
   L.status = take(256);
   L.total = o;
@@ -185,6 +186,8 @@ thread_local std::string g_create_error;
 
 }  // namespace
 
+struct lbmdem_batch;
+
 struct lbmdem_domain {
   lbmdem_config cfg;
   DevDomain d;
@@ -192,9 +195,6 @@ struct lbmdem_domain {
   hipStream_t stream = nullptr;
   void* region = nullptr;
   bool owns = false;
-  int cur = 0;
-  uint32_t stamp = 0;
-  int64_t steps = 0;
   int failed = 0;
   std::string err;
   std::vector<double> hx, hR;  // host shadow for insertion checks
@@ -209,6 +209,7 @@ struct lbmdem_domain {
   int64_t cnt[3] = {0, 0, 0};
   int grid_cap = 0;                   // co-resident blocks of the grid-wide DEM kernel
   unsigned long long bar_base = 0;    // arrivals at the grid-wide barriers so far
+  lbmdem_batch* batch = nullptr;      // batch the domain is admitted to
 };
 
 static int32_t fail(lbmdem_domain* dom, int32_t code, const std::string& msg) {
@@ -269,9 +270,8 @@ static void timed(lbmdem_domain* dom, int kind, hipStream_t s, F&& launch) {
 }
 
 static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
-  dom->stamp += 1;
   dom->d.P = (int)dom->hR.size();
-  timed(dom, 2, dom->stream, [&] { launch_mapping(dom->d, dom->cur, dom->stamp, reconstruct, dom->stream); });
+  timed(dom, 2, dom->stream, [&] { launch_mapping(dom->d, reconstruct, dom->stream); });
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;
 }
@@ -403,6 +403,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   bin_dims(*cfg, d.bins.n);
   d.bins.cell = (int*)(base + L.bins);
   d.barrier = (unsigned long long*)(base + L.barrier);
+  d.ctl = (DevCtl*)(base + L.ctl);
   d.P = 0;
   d.ZB = zblocks(*cfg);
   d.RB = rowblocks(*cfg);
@@ -453,6 +454,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
 
 int32_t lbmdem_destroy(lbmdem_domain* dom) {
   if (!dom) return LBMDEM_OK;
+  if (dom->batch) (void)lbmdem_batch_retire(dom->batch, dom);
   (void)hipStreamSynchronize(dom->stream);
   harvest(dom);
   for (auto e : dom->spare) (void)hipEventDestroy(e);
@@ -618,25 +620,23 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, con
 int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   if (!dom || nsteps < 0) return LBMDEM_EINVAL;
   if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  if (dom->batch) return fail(dom, LBMDEM_EINVAL, "domain is stepped by its batch");
   dom->d.P = (int)dom->hR.size();
   // One stream, back to back: the sweep (A -> B), the DEM sub-cycles and the
   // claims of the new positions, then reconstruction and the boundary pass
   // that commits the mapping and prepares the next step's links.
   for (int s = 0; s < nsteps; ++s) {
-    timed(dom, 0, dom->stream, [&] { launch_sweep(dom->d, dom->cur, dom->stream); });
-    dom->stamp += 1;
+    timed(dom, 0, dom->stream, [&] { launch_sweep(dom->d, dom->stream); });
     hipError_t e = hipSuccess;
     timed(dom, 1, dom->stream, [&] {
       e = launch_dem(dom->d, dom->cfg.dem_kernel, dom->grid_cap, &dom->bar_base, dom->stream);
-      launch_claim(dom->d, dom->stamp, dom->stream);
+      launch_claim(dom->d, dom->stream);
     });
     if (e != hipSuccess) {
       dom->failed = 1;
       return fail(dom, LBMDEM_EDEVICE, std::string("DEM launch failed: ") + hipGetErrorString(e));
     }
-    dom->cur ^= 1;
-    timed(dom, 2, dom->stream, [&] { launch_update(dom->d, dom->cur, dom->stamp, true, dom->stream); });
-    dom->steps += 1;
+    timed(dom, 2, dom->stream, [&] { launch_update(dom->d, true, dom->stream); });
   }
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;
@@ -744,7 +744,7 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
   const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (field == LBMDEM_FIELD_FLAGS || field == LBMDEM_FIELD_OWNER) {
     std::vector<double> h(N);
-    launch_fields(dom->d, dom->cur, first, stage, st);
+    launch_fields(dom->d, first, stage, st);
     HIPCHK(dom, hipGetLastError());
     HIPCHK(dom, hipMemcpyAsync(h.data(), stage, 8 * N, hipMemcpyDeviceToHost, st));
     HIPCHK(dom, hipStreamSynchronize(st));
@@ -760,7 +760,7 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
     return LBMDEM_OK;
   }
   for (int k = 0; k < planes; ++k) {
-    launch_fields(dom->d, dom->cur, first + k, stage, st);
+    launch_fields(dom->d, first + k, stage, st);
     HIPCHK(dom, hipGetLastError());
     HIPCHK(dom, hipMemcpyAsync((char*)dst + 8 * N * (size_t)k, stage, 8 * N, kind, st));
     HIPCHK(dom, hipStreamSynchronize(st));
@@ -776,7 +776,7 @@ int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
   hipStream_t st = dom->stream;
   for (int q = 0; q < Q; ++q) {
     HIPCHK(dom, hipMemcpyAsync(stage, f + (size_t)q * N, 8 * N, hipMemcpyHostToDevice, st));
-    launch_set_pdf(dom->d, dom->cur + 2 * q, stage, st);
+    launch_set_pdf(dom->d, q, stage, st);
     HIPCHK(dom, hipGetLastError());
     HIPCHK(dom, hipStreamSynchronize(st));
   }
@@ -796,9 +796,8 @@ struct CkHeader {
   uint32_t version;
   uint32_t cfg_bytes;
   lbmdem_config cfg;
-  int64_t steps;
-  uint32_t stamp;
   int32_t cur;
+  int32_t pad0;
   uint64_t bar_base;
   int32_t P;
   int32_t pad;
@@ -822,10 +821,10 @@ bool same_config(const lbmdem_config& a, const lbmdem_config& b) {
 
 // device segments of a checkpoint: the current PDF buffer, the cell arrays
 // (flags, owner, claims, shell stamps) and the particle block
-void ck_segments(const lbmdem_domain* dom, char** at, size_t* len) {
+void ck_segments(const lbmdem_domain* dom, int cur, char** at, size_t* len) {
   char* base = (char*)dom->region;
   const Layout& L = dom->L;
-  at[0] = base + (dom->cur ? L.pdf1 : L.pdf0);
+  at[0] = base + (cur ? L.pdf1 : L.pdf0);
   len[0] = L.pdf1 - L.pdf0;
   at[1] = base + L.flags;
   len[1] = L.stage - L.flags;
@@ -835,11 +834,19 @@ void ck_segments(const lbmdem_domain* dom, char** at, size_t* len) {
 
 }  // namespace
 
+static int32_t read_ctl(lbmdem_domain* dom, DevCtl* c) {
+  HIPCHK(dom, hipMemcpyAsync(c, dom->d.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, dom->stream));
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  return LBMDEM_OK;
+}
+
 int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes) {
   if (!dom || !bytes) return LBMDEM_EINVAL;
+  DevCtl c;
+  if (int32_t rc = read_ctl(dom, &c)) return rc;
   char* at[3];
   size_t len[3];
-  ck_segments(dom, at, len);
+  ck_segments(dom, c.cur, at, len);
   const size_t P = dom->hR.size();
   const size_t need = sizeof(CkHeader) + 8 * P + len[0] + len[1] + len[2];
   if (!host_blob) {
@@ -856,9 +863,7 @@ int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes) {
   h.version = CK_VERSION;
   h.cfg_bytes = sizeof(lbmdem_config);
   h.cfg = dom->cfg;
-  h.steps = dom->steps;
-  h.stamp = dom->stamp;
-  h.cur = dom->cur;
+  h.cur = c.cur;
   h.bar_base = dom->bar_base;
   h.P = (int32_t)P;
   for (int k = 0; k < 3; ++k) h.seg[k] = len[k];
@@ -867,7 +872,6 @@ int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes) {
   out += sizeof(h);
   if (P) std::memcpy(out, dom->hR.data(), 8 * P);
   out += 8 * P;
-  HIPCHK(dom, hipStreamSynchronize(dom->stream));
   for (int k = 0; k < 3; ++k) {
     HIPCHK(dom, hipMemcpyAsync(out, at[k], len[k], hipMemcpyDeviceToHost, dom->stream));
     out += len[k];
@@ -889,26 +893,49 @@ int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes) 
     return fail(dom, LBMDEM_EINVAL, "corrupt checkpoint header");
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
   harvest(dom);
-  dom->cur = h.cur;
   char* at[3];
   size_t len[3];
-  ck_segments(dom, at, len);
+  ck_segments(dom, h.cur, at, len);
   const size_t need = sizeof(CkHeader) + 8 * (size_t)h.P + len[0] + len[1] + len[2];
   if (bytes < need || h.seg[0] != len[0] || h.seg[1] != len[1] || h.seg[2] != len[2])
     return fail(dom, LBMDEM_EINVAL, "checkpoint size does not match this domain");
   const char* in = (const char*)host_blob + sizeof(h);
   dom->hR.assign((const double*)in, (const double*)in + h.P);
   in += 8 * (size_t)h.P;
+  // the step state (current buffer, stamp, step count) is part of the
+  // particle block
   for (int k = 0; k < 3; ++k) {
     HIPCHK(dom, hipMemcpyAsync(at[k], in, len[k], hipMemcpyHostToDevice, dom->stream));
     in += len[k];
   }
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
-  dom->steps = h.steps;
-  dom->stamp = h.stamp;
   dom->bar_base = h.bar_base;
   dom->d.P = h.P;
   dom->failed = 0;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_set_stop_rule(lbmdem_domain* dom, int32_t rule, int64_t max_steps) {
+  if (!dom) return LBMDEM_EINVAL;
+  if (rule != STOP_NONE && rule != STOP_REBOUND) return fail(dom, LBMDEM_EINVAL, "unknown stop rule");
+  DevCtl c;
+  if (int32_t rc = read_ctl(dom, &c)) return rc;
+  c.stop_rule = rule;
+  c.max_steps = max_steps;
+  c.stop_req = 0;
+  c.frozen = 0;
+  c.rb_phase = 0;
+  HIPCHK(dom, hipMemcpyAsync(dom->d.ctl, &c, sizeof(DevCtl), hipMemcpyHostToDevice, dom->stream));
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_get_progress(lbmdem_domain* dom, int64_t* steps, int32_t* stopped) {
+  if (!dom) return LBMDEM_EINVAL;
+  DevCtl c;
+  if (int32_t rc = read_ctl(dom, &c)) return rc;
+  if (steps) *steps = c.steps;
+  if (stopped) *stopped = (c.frozen || c.stop_req) ? 1 : 0;
   return LBMDEM_OK;
 }
 
@@ -947,5 +974,247 @@ int32_t lbmdem_device_copy(void* dst, const void* src, size_t bytes, void* hip_s
 const char* lbmdem_last_error(const lbmdem_domain* dom) {
   return dom ? dom->err.c_str() : g_create_error.c_str();
 }
+
+}  // extern "C"
+
+// ---- batches ------------------------------------------------------------------
+
+__global__ void k_batch_status(const DevDomain* __restrict__ tab, int ndom, long long* steps, int* stopped) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ndom) return;
+  const DevCtl* c = tab[k].ctl;
+  steps[k] = c->steps;
+  stopped[k] = (c->frozen || c->stop_req) ? 1 : 0;
+}
+
+struct lbmdem_batch {
+  hipStream_t stream = nullptr;
+  size_t pool = 0, used = 0;
+  int use_graph = 1;
+  int storage = -1;
+  std::vector<lbmdem_domain*> doms;
+  std::vector<int32_t> slots;
+  int32_t next_slot = 0;
+  // device tables: descriptors, block starts of the three launch kinds, status
+  void* dmem = nullptr;
+  size_t dmem_bytes = 0;
+  BatchTables t{};
+  long long* d_steps = nullptr;
+  int* d_stopped = nullptr;
+  bool dirty = true;
+  std::vector<int> built_P;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+static int32_t bfail(lbmdem_batch* b, int32_t code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define BHIPCHK(b, call)                                                                \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return bfail(b, LBMDEM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static void drop_graph(lbmdem_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// rebuilds the device tables when the admitted domains or their sphere counts
+// changed
+static int32_t build_tables(lbmdem_batch* b) {
+  const int nd = (int)b->doms.size();
+  std::vector<int> P(nd);
+  for (int k = 0; k < nd; ++k) P[k] = (int)b->doms[k]->hR.size();
+  if (!b->dirty && P == b->built_P) return LBMDEM_OK;
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  drop_graph(b);
+  std::vector<DevDomain> tab(nd);
+  std::vector<int> ss(nd + 1, 0), cs(nd + 1, 0), ms(nd + 1, 0);
+  for (int k = 0; k < nd; ++k) {
+    lbmdem_domain* dom = b->doms[k];
+    dom->d.P = P[k];
+    tab[k] = dom->d;
+    const DevDomain& d = dom->d;
+    ss[k + 1] = ss[k] + (int)((d.N + 255) / 256);
+    cs[k + 1] = cs[k] + d.P * d.ZB;
+    ms[k + 1] = ms[k] + d.P * d.ZB * d.RB + (wall_cell_count(d) + 255) / 256;
+  }
+  const size_t tb = align256(sizeof(DevDomain) * (size_t)std::max(nd, 1));
+  const size_t ib = align256(4 * (size_t)(nd + 1));
+  const size_t need = tb + 3 * ib + align256(8 * (size_t)std::max(nd, 1)) + align256(4 * (size_t)std::max(nd, 1));
+  if (need > b->dmem_bytes) {
+    if (b->dmem) BHIPCHK(b, hipFree(b->dmem));
+    b->dmem = nullptr;
+    b->dmem_bytes = 0;
+    BHIPCHK(b, hipMalloc(&b->dmem, need));
+    b->dmem_bytes = need;
+  }
+  char* m = (char*)b->dmem;
+  if (nd) BHIPCHK(b, hipMemcpyAsync(m, tab.data(), sizeof(DevDomain) * nd, hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(m + tb, ss.data(), 4 * (nd + 1), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(m + tb + ib, cs.data(), 4 * (nd + 1), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipMemcpyAsync(m + tb + 2 * ib, ms.data(), 4 * (nd + 1), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  b->t.tab = (const DevDomain*)m;
+  b->t.sweep_start = (const int*)(m + tb);
+  b->t.claim_start = (const int*)(m + tb + ib);
+  b->t.commit_start = (const int*)(m + tb + 2 * ib);
+  b->t.ndom = nd;
+  b->t.sweep_blocks = ss[nd];
+  b->t.claim_blocks = cs[nd];
+  b->t.commit_blocks = ms[nd];
+  b->t.storage = b->storage;
+  b->d_steps = (long long*)(m + tb + 3 * ib);
+  b->d_stopped = (int*)(m + tb + 3 * ib + align256(8 * (size_t)std::max(nd, 1)));
+  b->built_P = P;
+  b->dirty = false;
+  return LBMDEM_OK;
+}
+
+static void launch_batch_step(lbmdem_batch* b) {
+  launch_sweep_batch(b->t, b->stream);
+  launch_dem_batch(b->t, b->stream);
+  launch_mapping_batch(b->t, b->stream);
+}
+
+extern "C" {
+
+int32_t lbmdem_batch_create(void* hip_stream, size_t pool_bytes, lbmdem_batch** out) {
+  if (!out) return LBMDEM_EINVAL;
+  lbmdem_batch* b = new (std::nothrow) lbmdem_batch();
+  if (!b) return LBMDEM_ENOMEM;
+  b->stream = (hipStream_t)hip_stream;
+  b->pool = pool_bytes;
+  *out = b;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_destroy(lbmdem_batch* b) {
+  if (!b) return LBMDEM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  for (auto* d : b->doms) d->batch = nullptr;
+  if (b->dmem) (void)hipFree(b->dmem);
+  delete b;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_set_graph(lbmdem_batch* b, int32_t use_graph) {
+  if (!b) return LBMDEM_EINVAL;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  b->use_graph = use_graph ? 1 : 0;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_admit(lbmdem_batch* b, lbmdem_domain* dom, int32_t* slot) {
+  if (!b || !dom) return LBMDEM_EINVAL;
+  if (dom->failed) return bfail(b, LBMDEM_ESTATE, "domain has failed");
+  if (dom->batch) return bfail(b, LBMDEM_EINVAL, "domain already belongs to a batch");
+  if (dom->stream != b->stream) return bfail(b, LBMDEM_EINVAL, "domain was created on another stream");
+  if (b->storage >= 0 && dom->cfg.storage != b->storage)
+    return bfail(b, LBMDEM_EINVAL, "all domains of a batch share one storage precision");
+  if (dom->d.map_ball) return bfail(b, LBMDEM_EINVAL, "batched domains use the slab boundary pass (map_kernel 1)");
+  const size_t fp = dom->L.total;
+  if (b->used + fp > b->pool) return bfail(b, LBMDEM_ENOMEM, "pool budget exceeded");
+  b->storage = dom->cfg.storage;
+  b->used += fp;
+  b->doms.push_back(dom);
+  b->slots.push_back(b->next_slot);
+  if (slot) *slot = b->next_slot;
+  b->next_slot++;
+  dom->batch = b;
+  b->dirty = true;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_retire(lbmdem_batch* b, lbmdem_domain* dom) {
+  if (!b || !dom) return LBMDEM_EINVAL;
+  for (size_t k = 0; k < b->doms.size(); ++k)
+    if (b->doms[k] == dom) {
+      b->doms.erase(b->doms.begin() + k);
+      b->slots.erase(b->slots.begin() + k);
+      b->used -= dom->L.total;
+      dom->batch = nullptr;
+      b->dirty = true;
+      return LBMDEM_OK;
+    }
+  return bfail(b, LBMDEM_EINVAL, "domain is not in this batch");
+}
+
+int32_t lbmdem_batch_step(lbmdem_batch* b, int32_t nsteps) {
+  if (!b || nsteps < 0) return LBMDEM_EINVAL;
+  if (int32_t rc = build_tables(b)) return rc;
+  if (b->t.ndom == 0 || nsteps == 0) return LBMDEM_OK;
+  if (!b->use_graph) {
+    for (int s = 0; s < nsteps; ++s) launch_batch_step(b);
+    BHIPCHK(b, hipGetLastError());
+    return LBMDEM_OK;
+  }
+  if (!b->exec) {
+    BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    launch_batch_step(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return bfail(b, LBMDEM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  for (int s = 0; s < nsteps; ++s) BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_status(lbmdem_batch* b, int32_t* slots, int64_t* steps, int32_t* stopped, int32_t* n) {
+  if (!b || !n) return LBMDEM_EINVAL;
+  if (int32_t rc = build_tables(b)) return rc;
+  const int nd = b->t.ndom;
+  if (*n < nd) {
+    *n = nd;
+    return bfail(b, LBMDEM_EINVAL, "output arrays too small");
+  }
+  std::vector<long long> hs(nd);
+  std::vector<int> hf(nd);
+  if (nd) {
+    hipLaunchKernelGGL(k_batch_status, dim3((nd + 255) / 256), dim3(256), 0, b->stream, b->t.tab, nd, b->d_steps,
+                       b->d_stopped);
+    BHIPCHK(b, hipGetLastError());
+    BHIPCHK(b, hipMemcpyAsync(hs.data(), b->d_steps, 8 * nd, hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(hf.data(), b->d_stopped, 4 * nd, hipMemcpyDeviceToHost, b->stream));
+  }
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  for (int k = 0; k < nd; ++k) {
+    if (slots) slots[k] = b->slots[k];
+    if (steps) steps[k] = hs[k];
+    if (stopped) stopped[k] = hf[k];
+  }
+  *n = nd;
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_batch_done(lbmdem_batch* b, int32_t* slots, int32_t* n) {
+  if (!b || !n || (*n > 0 && !slots)) return LBMDEM_EINVAL;
+  const int cap = *n;
+  int32_t nd = (int32_t)b->doms.size();
+  std::vector<int32_t> sl(nd), st(nd);
+  if (int32_t rc = lbmdem_batch_status(b, sl.data(), nullptr, st.data(), &nd)) return rc;
+  int m = 0;
+  for (int k = 0; k < nd; ++k)
+    if (st[k]) {
+      if (m < cap) slots[m] = sl[k];
+      ++m;
+    }
+  *n = m;
+  return m > cap ? bfail(b, LBMDEM_EINVAL, "output array too small") : LBMDEM_OK;
+}
+
+const char* lbmdem_batch_last_error(const lbmdem_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

@@ -450,7 +450,66 @@ __device__ __forceinline__ void dem_body(const DevDomain& d, const DevParticles&
   for (int i = threadIdx.x; i < P; i += blockDim.x) health_check(d, p, i);
 }
 
-__global__ __launch_bounds__(256) void k_dem(DevDomain d) { dem_body(d, d.p); }
+// ---- step control -----------------------------------------------------------
+
+// At the start of the step's DEM kernel: true if the domain does not step (it
+// is frozen, or the stop rule was met at the end of the last step, in which
+// case it freezes now).  Every thread may call it; one writes.
+__device__ __forceinline__ bool dem_stopped(const DevDomain& d, bool writer) {
+  if (d.ctl->frozen) return true;
+  if (d.ctl->stop_req) {
+    if (writer) d.ctl->frozen = 1;
+    return true;
+  }
+  return false;
+}
+
+// At the end of the step's DEM work, by one thread: count the step, flip the
+// current PDF buffer (the sweep has written the other one), take a new mapping
+// stamp for the claims of the new positions, and evaluate the stop rule.  The
+// rebound rule follows sphere 0: approach, wall or sphere contact (collision
+// force of the last sub-cycle non-zero), contact over, rising (u_z > 0), apex
+// (u_z <= 0 again).
+__device__ __forceinline__ void advance_step(const DevDomain& d, const DevParticles& p) {
+  DevCtl* c = d.ctl;
+  c->steps += 1;
+  c->cur ^= 1;
+  c->stamp += 1;
+  bool stop = c->max_steps > 0 && c->steps >= c->max_steps;
+  if (c->stop_rule == STOP_REBOUND && d.P > 0) {
+    const bool contact = p.diag[12] != 0.0 || p.diag[13] != 0.0 || p.diag[14] != 0.0;
+    const double uz = p.u[2];
+    int ph = c->rb_phase;
+    if (ph == 0 && contact)
+      ph = 1;
+    else if (ph == 1 && !contact)
+      ph = 2;
+    else if (ph == 2 && uz > 0.0)
+      ph = 3;
+    else if (ph == 3 && uz <= 0.0)
+      stop = true;
+    c->rb_phase = ph;
+  }
+  if (stop) c->stop_req = 1;
+}
+
+// the step without spheres: control only
+__global__ void k_step_ctl(DevDomain d) {
+  if (dem_stopped(d, true)) return;
+  advance_step(d, d.p);
+}
+
+// one workgroup, state in global memory
+__device__ __forceinline__ void dem_global_run(const DevDomain& d) {
+  dem_body(d, d.p);
+  __syncthreads();
+  if (threadIdx.x == 0) advance_step(d, d.p);
+}
+
+__global__ __launch_bounds__(256) void k_dem(DevDomain d) {
+  if (dem_stopped(d, threadIdx.x == 0)) return;
+  dem_global_run(d);
+}
 
 // Few spheres: their state, contact histories and neighbour lists live in LDS
 // for the whole step, so the sub-cycles (separated by workgroup barriers) do
@@ -459,7 +518,7 @@ constexpr int DEM_LDS_MAX = 32;
 // automatic choice: above this many spheres the grid-wide kernel
 constexpr int DEM_GRID_MIN = 256;
 
-__global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
+__device__ __forceinline__ void dem_lds_run(const DevDomain& d) {
   constexpr int PS = DEM_LDS_MAX;
   __shared__ double sx[3 * PS], su[3 * PS], sw[3 * PS], sR[PS], sm[PS], sI[PS], srho[PS], stp[PS];
   __shared__ double spresc[6 * PS], sFfp[6 * PS], sFold[6 * PS], sdiag[18 * PS], sFnew[6 * PS];
@@ -531,6 +590,27 @@ __global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
       for (int a = 0; a < 3; ++a) g.hist_d[3 * ((size_t)HIST_SLOTS * t + k) + a] = shd[3 * (HIST_SLOTS * t + k) + a];
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) advance_step(d, g);
+}
+
+__global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
+  if (dem_stopped(d, threadIdx.x == 0)) return;
+  dem_lds_run(d);
+}
+
+// many domains, one workgroup each (the few-sphere kernels above)
+__global__ __launch_bounds__(256) void k_dem_batch(const DevDomain* __restrict__ tab, int ndom) {
+  const DevDomain& d = tab[blockIdx.x];
+  if (dem_stopped(d, threadIdx.x == 0)) return;
+  if (d.P <= DEM_LDS_MAX)
+    dem_lds_run(d);
+  else
+    dem_global_run(d);
+}
+
+void launch_dem_batch(const BatchTables& b, hipStream_t s) {
+  if (b.ndom > 0) hipLaunchKernelGGL(k_dem_batch, dim3(b.ndom), dim3(256), 0, s, b.tab, b.ndom);
 }
 
 // ---------------------------------------------------------------------------
@@ -650,7 +730,17 @@ __device__ __forceinline__ void binned_neighbours(const DevDomain& d, const DevP
   p.nbr_n[i] = cnt < NBR_MAX ? cnt : NBR_MAX;
 }
 
+// barriers of one grid-wide launch: two in the prologue, two per sub-cycle
+__host__ __device__ inline unsigned long long grid_barriers(const DevDomain& d) {
+  return 2ull + 2ull * (unsigned long long)d.n_sub;
+}
+
 __global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsigned long long base) {
+  if (dem_stopped(d, blockIdx.x == 0 && threadIdx.x == 0)) {
+    // keep the arrival count what the host expects for this launch
+    if (threadIdx.x == 0) atomicAdd(d.barrier, grid_barriers(d));
+    return;
+  }
   __shared__ int broken;
   if (threadIdx.x == 0) broken = 0;
   __syncthreads();
@@ -707,6 +797,8 @@ __global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsi
       }
     health_check(d, p, i);
   }
+  // sphere 0 was advanced by this very thread
+  if (blockIdx.x == 0 && threadIdx.x == 0) advance_step(d, p);
 }
 
 int dem_grid_capacity() {
@@ -719,12 +811,12 @@ int dem_grid_capacity() {
   return nb * ncu;
 }
 
-// barriers of one grid-wide launch: two in the prologue, two per sub-cycle
-static unsigned long long grid_barriers(const DevDomain& d) { return 2ull + 2ull * (unsigned long long)d.n_sub; }
-
 hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
                       hipStream_t s) {
-  if (d.P <= 0) return hipSuccess;
+  if (d.P <= 0) {
+    hipLaunchKernelGGL(k_step_ctl, dim3(1), dim3(1), 0, s, d);
+    return hipGetLastError();
+  }
   const bool grid = kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN);
   if (!grid) {
     if (d.P <= DEM_LDS_MAX)

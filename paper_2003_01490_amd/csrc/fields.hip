@@ -40,7 +40,8 @@ __device__ inline double to_d<__half>(__half v) {
 // which: 0 rho, 1..3 velocity component, 10+q PDF plane q (full f),
 // 40 canonical flags, 41 owner (as double)
 template <typename T>
-__global__ void k_get_plane(DevDomain d, int cur, int which, double* dst) {
+__global__ void k_get_plane(DevDomain d, int which, double* dst) {
+  const int cur = d.ctl->cur;
   const size_t N = (size_t)d.N;
   const T* f = (const T*)d.pdf[cur];
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
@@ -80,7 +81,8 @@ __device__ inline __half from_d<__half>(double v) {
 }
 
 template <typename T>
-__global__ void k_set_plane(DevDomain d, int cur, int q, const double* src) {
+__global__ void k_set_plane(DevDomain d, int q, const double* src) {
+  const int cur = d.ctl->cur;
   const size_t N = (size_t)d.N;
   T* f = (T*)d.pdf[cur];
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
@@ -116,24 +118,23 @@ void launch_fill_claims(const DevDomain& d, hipStream_t s) {
     hipLaunchKernelGGL(k_init<__half>, grid_for(d.N), dim3(256), 0, s, d);
 }
 
-void launch_fields(const DevDomain& d, int cur, int which, double* dst, hipStream_t s) {
+void launch_fields(const DevDomain& d, int which, double* dst, hipStream_t s) {
   if (d.storage == 0)
-    hipLaunchKernelGGL(k_get_plane<double>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+    hipLaunchKernelGGL(k_get_plane<double>, grid_for(d.N), dim3(256), 0, s, d, which, dst);
   else if (d.storage == 1)
-    hipLaunchKernelGGL(k_get_plane<float>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+    hipLaunchKernelGGL(k_get_plane<float>, grid_for(d.N), dim3(256), 0, s, d, which, dst);
   else
-    hipLaunchKernelGGL(k_get_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, cur, which, dst);
+    hipLaunchKernelGGL(k_get_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, which, dst);
 }
 
-// src: one plane q (encoded in the upper bits of `cur`: cur + 2*q)
-void launch_set_pdf(const DevDomain& d, int curq, const double* src, hipStream_t s) {
-  const int cur = curq & 1, q = curq >> 1;
+// src: the full distribution of direction q on every cell
+void launch_set_pdf(const DevDomain& d, int q, const double* src, hipStream_t s) {
   if (d.storage == 0)
-    hipLaunchKernelGGL(k_set_plane<double>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+    hipLaunchKernelGGL(k_set_plane<double>, grid_for(d.N), dim3(256), 0, s, d, q, src);
   else if (d.storage == 1)
-    hipLaunchKernelGGL(k_set_plane<float>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+    hipLaunchKernelGGL(k_set_plane<float>, grid_for(d.N), dim3(256), 0, s, d, q, src);
   else
-    hipLaunchKernelGGL(k_set_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, cur, q, src);
+    hipLaunchKernelGGL(k_set_plane<__half>, grid_for(d.N), dim3(256), 0, s, d, q, src);
 }
 
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {

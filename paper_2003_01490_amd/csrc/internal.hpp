@@ -54,6 +54,27 @@ static __constant__ const double WQ[Q] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18
                                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
+// Step state of a domain, resident on the device so that a step needs no
+// per-step kernel arguments (graph replay, batched launches) and a domain can
+// stop on the device.  The DEM kernel (run every step, also without spheres)
+// advances it after the sweep: cur flips, stamp and steps increase, and the
+// stop rule is evaluated; a stop freezes the domain at the start of the next
+// step, before its mapping could change (that step's sweep output goes to the
+// spare buffer and is dropped).
+struct DevCtl {
+  uint32_t stamp;     // claims and shell stamps of the current mapping
+  int32_t cur;        // PDF buffer holding the current post-collision state
+  int32_t frozen;     // 1: every kernel of this domain returns at once
+  int32_t stop_req;   // the stop rule was met at the end of the last step
+  int64_t steps;      // coupled steps done
+  int64_t max_steps;  // stop after this many steps (<= 0: never)
+  int32_t stop_rule;  // 0 none, 1 rebound of sphere 0 (first apex after its first wall contact)
+  int32_t rb_phase;   // rebound tracking: 0 approach, 1 contact, 2 after contact, 3 rising
+};
+
+constexpr int STOP_NONE = 0;
+constexpr int STOP_REBOUND = 1;
+
 struct DevParticles {
   double* x;      // [P][3] position
   double* u;      // [P][3]
@@ -114,6 +135,7 @@ struct DevDomain {
   int stage_edge;  // edge of the LDS-staged cube of k_commit_ball (odd)
   int list_cap;    // surface-cell list capacity of k_commit_ball
   int* status;
+  DevCtl* ctl;
   // DEM parameters
   int n_sub;
   int force_averaging;
@@ -146,14 +168,50 @@ __device__ inline double min_image(double v, int n, int wall) {
   return v;
 }
 
+// Device tables of a batch of domains (one launch per kernel for all of them):
+// descriptors, and for each kernel the first block of every domain (ndom + 1
+// entries, the last one the total).
+struct BatchTables {
+  const DevDomain* tab;
+  const int* sweep_start;
+  const int* claim_start;   // P * ZB blocks per domain (claims, reconstruction)
+  const int* commit_start;  // P * ZB * RB sphere blocks + wall blocks per domain
+  int ndom;
+  int sweep_blocks, claim_blocks, commit_blocks;
+  int storage;
+};
+
+// domain of block b: the k with start[k] <= b < start[k+1] (binary search)
+__device__ __forceinline__ int batch_domain(const int* start, int ndom, int b) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// cells of the wall layers (boundary values of moving-wall bounce-back)
+__host__ __device__ inline int wall_cell_count(const DevDomain& d) {
+  int n = 0;
+  const int nzi = d.nz - 2 * d.walls[2], nyi = d.ny - 2 * d.walls[1];
+  if (d.walls[2]) n += 2 * d.nx * d.ny;
+  if (d.walls[1]) n += 2 * d.nx * nzi;
+  if (d.walls[0]) n += 2 * nyi * nzi;
+  return n;
+}
+
 // host-side launchers (implemented in the .hip files)
-void launch_sweep(const DevDomain& d, int cur, hipStream_t s);
-// claim + (reconstruction) + commit/boundary values, in order on one stream
-void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
-                    hipStream_t s);
+void launch_sweep(const DevDomain& d, hipStream_t s);
+// a new mapping stamp, then claim + (reconstruction) + commit/boundary values,
+// in order on one stream (mapping updates outside the step)
+void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s);
 // the claim kernel alone (needs only the particle positions), and the rest
-void launch_claim(const DevDomain& d, uint32_t stamp, hipStream_t s);
-void launch_update(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s);
+void launch_claim(const DevDomain& d, hipStream_t s);
+void launch_update(const DevDomain& d, bool reconstruct, hipStream_t s);
 // DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 grid-wide
 // (cooperative).  *barrier_base is the arrival count the grid barriers start
 // from; it is advanced by the arrivals of the launch.
@@ -163,9 +221,13 @@ hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned lon
 // co-resident blocks of the grid-wide DEM kernel on the current device
 int dem_grid_capacity();
 constexpr int DEM_GRID_THREADS = 128;
-void launch_fields(const DevDomain& d, int cur, int field, double* dst, hipStream_t s);
-void launch_set_pdf(const DevDomain& d, int cur, const double* src, hipStream_t s);
+void launch_fields(const DevDomain& d, int field, double* dst, hipStream_t s);
+void launch_set_pdf(const DevDomain& d, int q, const double* src, hipStream_t s);
 void launch_fill_claims(const DevDomain& d, hipStream_t s);
+// batched step kernels over the domains of a batch
+void launch_sweep_batch(const BatchTables& b, hipStream_t s);
+void launch_dem_batch(const BatchTables& b, hipStream_t s);
+void launch_mapping_batch(const BatchTables& b, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace lbmdem

@@ -47,6 +47,7 @@ __device__ inline void sphere_box(const DevDomain& d, int i, bool with_old, Box&
   for (int a = 0; a < 3; ++a)
     finite = finite && isfinite(d.p.x[3 * i + a]) && (!with_old || isfinite(d.p.xmap[3 * i + a]));
   if (!finite) {
+#pragma unroll
     for (int a = 0; a < 3; ++a) b.lo[a] = b.ext[a] = 0;
     return;
   }
@@ -129,8 +130,8 @@ __device__ inline void stv<__half>(__half* p, double v) { *p = __float2half_rn((
     }                                                                                \
   }
 
-__global__ __launch_bounds__(256) void k_claim(DevDomain d, uint32_t stamp) {
-  const int i = blockIdx.x / d.ZB, b = blockIdx.x % d.ZB;
+__device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_t stamp) {
+  const int i = blk / d.ZB, b = blk % d.ZB;
   if (i >= d.P) return;
   Box bx;
   sphere_box(d, i, false, bx);
@@ -154,6 +155,14 @@ __global__ __launch_bounds__(256) void k_claim(DevDomain d, uint32_t stamp) {
     }
   })
 }
+
+__global__ __launch_bounds__(256) void k_claim(DevDomain d) {
+  if (d.ctl->frozen) return;
+  claim_block(d, blockIdx.x, d.ctl->stamp);
+}
+
+// a new mapping stamp (mapping updates outside the step)
+__global__ void k_new_stamp(DevCtl* ctl) { ctl->stamp += 1; }
 
 // Eq. (PDF_reconstruction) for cell (ii,jj,kk) formerly covered by sphere i
 template <typename T>
@@ -323,8 +332,8 @@ __device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, lon
 constexpr int RECON_LIST = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_recon(DevDomain d, int cur, uint32_t stamp) {
-  const int i = blockIdx.x / d.ZB, b = blockIdx.x % d.ZB;
+__device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur, uint32_t stamp) {
+  const int i = blk / d.ZB, b = blk % d.ZB;
   if (i >= d.P) return;
   __shared__ long long cand[RECON_LIST];
   __shared__ int ncand;
@@ -364,6 +373,12 @@ __global__ __launch_bounds__(256) void k_recon(DevDomain d, int cur, uint32_t st
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   for (int e = wave; e < n; e += nwave) reconstruct_wave<T>(d, buf, stamp, cand[e], i, lane);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon(DevDomain d) {
+  if (d.ctl->frozen) return;
+  recon_block<T>(d, blockIdx.x, d.ctl->cur, d.ctl->stamp);
 }
 
 // smallest root in [0,1] of |r + delta c|^2 = R^2 (x_b = x + delta_q c_q)
@@ -552,16 +567,16 @@ __device__ __forceinline__ void wall_cell_values(const DevDomain& d, T* buf, uin
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t stamp, int nwall) {
+__device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cur, uint32_t stamp, int nwall) {
   const int nsb = d.P * d.ZB * d.RB;
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
-  if ((int)blockIdx.x >= nsb) {
-    wall_cell_values<T>(d, buf, stamp, (blockIdx.x - nsb) * blockDim.x + threadIdx.x, nwall);
+  if (blk >= nsb) {
+    wall_cell_values<T>(d, buf, stamp, (blk - nsb) * blockDim.x + threadIdx.x, nwall);
     return;
   }
   const int nbs = d.ZB * d.RB;
-  const int i = blockIdx.x / nbs, b = blockIdx.x % nbs;
+  const int i = blk / nbs, b = blk % nbs;
   const int bz = b / d.RB, brow = b % d.RB;
   Box bx;
   sphere_box(d, i, true, bx);
@@ -675,6 +690,12 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t s
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_commit(DevDomain d, int nwall) {
+  if (d.ctl->frozen) return;
+  commit_block<T>(d, blockIdx.x, d.ctl->cur, d.ctl->stamp, nwall);
+}
+
 // Many spheres: one block per sphere.  The states of all cells within R + 3 of
 // the new centre (every cell a link of the sphere or its CLI neighbour can
 // touch) are staged in LDS in one pass with many loads in flight; then the
@@ -685,7 +706,10 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int cur, uint32_t s
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int cur, uint32_t stamp, int nwall) {
+__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int nwall) {
+  if (d.ctl->frozen) return;
+  const int cur = d.ctl->cur;
+  const uint32_t stamp = d.ctl->stamp;
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
   const int P = d.P;
@@ -863,51 +887,89 @@ __global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int cur, uint3
   }
 }
 
-static int wall_cell_count(const DevDomain& d) {
-  int n = 0;
-  const int nzi = d.nz - 2 * d.walls[2], nyi = d.ny - 2 * d.walls[1];
-  if (d.walls[2]) n += 2 * d.nx * d.ny;
-  if (d.walls[1]) n += 2 * d.nx * nzi;
-  if (d.walls[0]) n += 2 * nyi * nzi;
-  return n;
-}
 
-void launch_claim(const DevDomain& d, uint32_t stamp, hipStream_t s) {
+void launch_claim(const DevDomain& d, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, stamp);
+  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d);
 }
 
 template <typename T>
-static void launch_update_t(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct,
-                            hipStream_t s) {
+static void launch_update_t(const DevDomain& d, bool reconstruct, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0 && reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, cur, stamp);
+  if (nsb > 0 && reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d);
   const int nwall = wall_cell_count(d);
   const int wblocks = (nwall + 255) / 256;
   if (d.map_ball) {
     const size_t lds = (((size_t)d.stage_edge * d.stage_edge * d.stage_edge + 15) & ~(size_t)15) +
                        2 * (size_t)d.list_cap;
     if (d.P + wblocks > 0)
-      hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P + wblocks), dim3(256), lds, s, d, cur, stamp, nwall);
+      hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P + wblocks), dim3(256), lds, s, d, nwall);
     return;
   }
   const int ncb = nsb * d.RB;
-  if (ncb + wblocks > 0)
-    hipLaunchKernelGGL(k_commit<T>, dim3(ncb + wblocks), dim3(256), 0, s, d, cur, stamp, nwall);
+  if (ncb + wblocks > 0) hipLaunchKernelGGL(k_commit<T>, dim3(ncb + wblocks), dim3(256), 0, s, d, nwall);
 }
 
-void launch_update(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s) {
+void launch_update(const DevDomain& d, bool reconstruct, hipStream_t s) {
   if (d.storage == 0)
-    launch_update_t<double>(d, cur, stamp, reconstruct, s);
+    launch_update_t<double>(d, reconstruct, s);
   else if (d.storage == 1)
-    launch_update_t<float>(d, cur, stamp, reconstruct, s);
+    launch_update_t<float>(d, reconstruct, s);
   else
-    launch_update_t<__half>(d, cur, stamp, reconstruct, s);
+    launch_update_t<__half>(d, reconstruct, s);
 }
 
-void launch_mapping(const DevDomain& d, int cur, uint32_t stamp, bool reconstruct, hipStream_t s) {
-  launch_claim(d, stamp, s);
-  launch_update(d, cur, stamp, reconstruct, s);
+void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
+  hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
+  launch_claim(d, s);
+  launch_update(d, reconstruct, s);
+}
+
+// ---- batched mapping update (slab blocks; one launch per kernel for all domains)
+
+__global__ __launch_bounds__(256) void k_claim_batch(const DevDomain* __restrict__ tab, const int* __restrict__ start,
+                                                     int ndom) {
+  const int k = batch_domain(start, ndom, (int)blockIdx.x);
+  const DevDomain& d = tab[k];
+  if (d.ctl->frozen) return;
+  claim_block(d, (int)blockIdx.x - start[k], d.ctl->stamp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon_batch(const DevDomain* __restrict__ tab, const int* __restrict__ start,
+                                                     int ndom) {
+  const int k = batch_domain(start, ndom, (int)blockIdx.x);
+  const DevDomain& d = tab[k];
+  if (d.ctl->frozen) return;
+  recon_block<T>(d, (int)blockIdx.x - start[k], d.ctl->cur, d.ctl->stamp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_commit_batch(const DevDomain* __restrict__ tab, const int* __restrict__ start,
+                                                      int ndom) {
+  const int k = batch_domain(start, ndom, (int)blockIdx.x);
+  const DevDomain& d = tab[k];
+  if (d.ctl->frozen) return;
+  commit_block<T>(d, (int)blockIdx.x - start[k], d.ctl->cur, d.ctl->stamp, wall_cell_count(d));
+}
+
+template <typename T>
+static void launch_mapping_batch_t(const BatchTables& b, hipStream_t s) {
+  if (b.claim_blocks > 0) {
+    hipLaunchKernelGGL(k_claim_batch, dim3(b.claim_blocks), dim3(256), 0, s, b.tab, b.claim_start, b.ndom);
+    hipLaunchKernelGGL(k_recon_batch<T>, dim3(b.claim_blocks), dim3(256), 0, s, b.tab, b.claim_start, b.ndom);
+  }
+  if (b.commit_blocks > 0)
+    hipLaunchKernelGGL(k_commit_batch<T>, dim3(b.commit_blocks), dim3(256), 0, s, b.tab, b.commit_start, b.ndom);
+}
+
+void launch_mapping_batch(const BatchTables& b, hipStream_t s) {
+  if (b.storage == 0)
+    launch_mapping_batch_t<double>(b, s);
+  else if (b.storage == 1)
+    launch_mapping_batch_t<float>(b, s);
+  else
+    launch_mapping_batch_t<__half>(b, s);
 }
 
 }  // namespace lbmdem

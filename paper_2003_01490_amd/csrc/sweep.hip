@@ -48,18 +48,13 @@ struct Store<__half> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ src, T* __restrict__ dst,
-                                               const uint8_t* __restrict__ flags, int nx, int ny,
-                                               int nz, unsigned int N,
-                                               typename Store<T>::C sp,
-                                               typename Store<T>::C sm,
-                                               typename Store<T>::C db_shell,
-                                               typename Store<T>::C db_other) {
+__device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restrict__ dst,
+                                           const uint8_t* __restrict__ flags, int x, int y, int z,
+                                           int nx, int ny, int nz, unsigned int N,
+                                           typename Store<T>::C sp, typename Store<T>::C sm,
+                                           typename Store<T>::C db_shell,
+                                           typename Store<T>::C db_other) {
   using C = typename Store<T>::C;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= nx || y >= ny) return;
   const unsigned int nxy = (unsigned int)nx * (unsigned int)ny;
   const unsigned int idx = (unsigned int)x + (unsigned int)nx * (unsigned int)y + nxy * (unsigned int)z;
   const uint8_t fl = flags[idx];
@@ -152,8 +147,45 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ src, T* __r
   for (int q = 0; q < Q; ++q) Store<T>::store(dst + (size_t)q * NN + idx, o[q]);
 }
 
+// one domain: whole x-rows per block (see launch_sweep_t); the current buffer
+// is read from the domain's step state
 template <typename T>
-static void launch_sweep_t(const DevDomain& d, int cur, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_sweep(T* __restrict__ pa, T* __restrict__ pb,
+                                               const uint8_t* __restrict__ flags, const DevCtl* ctl,
+                                               int nx, int ny, int nz, unsigned int N,
+                                               typename Store<T>::C sp, typename Store<T>::C sm,
+                                               typename Store<T>::C db_shell,
+                                               typename Store<T>::C db_other) {
+  if (ctl->frozen) return;
+  const int cur = ctl->cur;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  sweep_cell<T>(cur ? pb : pa, cur ? pa : pb, flags, x, y, blockIdx.z, nx, ny, nz, N, sp, sm, db_shell,
+                db_other);
+}
+
+// many domains in one launch: block b belongs to the domain k with
+// start[k] <= b < start[k+1] and covers 256 consecutive cells of it
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_batch(const DevDomain* __restrict__ tab,
+                                                     const int* __restrict__ start, int ndom) {
+  using C = typename Store<T>::C;
+  const int k = batch_domain(start, ndom, (int)blockIdx.x);
+  const DevDomain& d = tab[k];
+  if (d.ctl->frozen) return;
+  const long long c = (long long)(blockIdx.x - start[k]) * 256 + threadIdx.x;
+  if (c >= d.N) return;
+  const int x = (int)(c % d.nx), y = (int)((c / d.nx) % d.ny), z = (int)(c / ((long long)d.nx * d.ny));
+  const int cur = d.ctl->cur;
+  T* pa = (T*)d.pdf[0];
+  T* pb = (T*)d.pdf[1];
+  sweep_cell<T>(cur ? pb : pa, cur ? pa : pb, d.flags, x, y, z, d.nx, d.ny, d.nz, (unsigned int)d.N,
+                (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
+}
+
+template <typename T>
+static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
   dim3 block, grid;
   if (d.nx <= 256) {
     // whole rows per block: the periodic x-wrap stays inside the block
@@ -174,18 +206,28 @@ static void launch_sweep_t(const DevDomain& d, int cur, hipStream_t s) {
   grid.y = (d.ny + block.y - 1) / block.y;
   grid.z = d.nz;
   using C = typename Store<T>::C;
-  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, (const T*)d.pdf[cur], (T*)d.pdf[1 - cur],
-                     (const uint8_t*)d.flags, d.nx, d.ny, d.nz, (unsigned int)d.N, (C)d.s_plus,
+  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, (T*)d.pdf[0], (T*)d.pdf[1], (const uint8_t*)d.flags,
+                     (const DevCtl*)d.ctl, d.nx, d.ny, d.nz, (unsigned int)d.N, (C)d.s_plus,
                      (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
 }
 
-void launch_sweep(const DevDomain& d, int cur, hipStream_t s) {
+void launch_sweep(const DevDomain& d, hipStream_t s) {
   if (d.storage == 0)
-    launch_sweep_t<double>(d, cur, s);
+    launch_sweep_t<double>(d, s);
   else if (d.storage == 1)
-    launch_sweep_t<float>(d, cur, s);
+    launch_sweep_t<float>(d, s);
   else
-    launch_sweep_t<__half>(d, cur, s);
+    launch_sweep_t<__half>(d, s);
+}
+
+void launch_sweep_batch(const BatchTables& b, hipStream_t s) {
+  if (b.sweep_blocks <= 0) return;
+  if (b.storage == 0)
+    hipLaunchKernelGGL(k_sweep_batch<double>, dim3(b.sweep_blocks), dim3(256), 0, s, b.tab, b.sweep_start, b.ndom);
+  else if (b.storage == 1)
+    hipLaunchKernelGGL(k_sweep_batch<float>, dim3(b.sweep_blocks), dim3(256), 0, s, b.tab, b.sweep_start, b.ndom);
+  else
+    hipLaunchKernelGGL(k_sweep_batch<__half>, dim3(b.sweep_blocks), dim3(256), 0, s, b.tab, b.sweep_start, b.ndom);
 }
 
 }  // namespace lbmdem

@@ -22,6 +22,7 @@ TRT_AB, TRT_B, TRT, SRT = 0, 1, 2, 3
 BC_CLI, BC_BOUNCE_BACK = 0, 1
 STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
 FREE, PRESCRIBED, FIXED = 0, 1, 2
+STOP_NONE, STOP_REBOUND = 0, 1
 FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_FLAGS, FIELD_OWNER = 0, 1, 2, 3, 4
 SPHERE_STATE = 42
 
@@ -87,6 +88,17 @@ def lib():
         "lbmdem_set_pdf": (C.c_int32, [vp, dp]),
         "lbmdem_save": (C.c_int32, [vp, vp, C.POINTER(C.c_size_t)]),
         "lbmdem_restore": (C.c_int32, [vp, vp, C.c_size_t]),
+        "lbmdem_set_stop_rule": (C.c_int32, [vp, C.c_int32, C.c_int64]),
+        "lbmdem_get_progress": (C.c_int32, [vp, C.POINTER(C.c_int64), ip]),
+        "lbmdem_batch_create": (C.c_int32, [vp, C.c_size_t, C.POINTER(vp)]),
+        "lbmdem_batch_destroy": (C.c_int32, [vp]),
+        "lbmdem_batch_set_graph": (C.c_int32, [vp, C.c_int32]),
+        "lbmdem_batch_admit": (C.c_int32, [vp, vp, ip]),
+        "lbmdem_batch_retire": (C.c_int32, [vp, vp]),
+        "lbmdem_batch_step": (C.c_int32, [vp, C.c_int32]),
+        "lbmdem_batch_status": (C.c_int32, [vp, ip, C.POINTER(C.c_int64), ip, ip]),
+        "lbmdem_batch_done": (C.c_int32, [vp, ip, ip]),
+        "lbmdem_batch_last_error": (C.c_char_p, [vp]),
         "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
         "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
         "lbmdem_sweep_bytes": (C.c_double, [vp]),
@@ -254,6 +266,16 @@ class Domain:
     def restore(self, blob: bytes):
         self._check(lib().lbmdem_restore(self.h, blob, len(blob)))
 
+    # --- stop rule --------------------------------------------------------
+    def set_stop_rule(self, rule=STOP_NONE, max_steps=0):
+        self._check(lib().lbmdem_set_stop_rule(self.h, int(rule), int(max_steps)))
+
+    def progress(self):
+        """(steps done, stopped)"""
+        n, st = C.c_int64(0), C.c_int32(0)
+        self._check(lib().lbmdem_get_progress(self.h, C.byref(n), C.byref(st)))
+        return n.value, bool(st.value)
+
     # --- time stepping ----------------------------------------------------
     def step(self, n=1):
         self._check(lib().lbmdem_step(self.h, int(n)))
@@ -304,6 +326,80 @@ class Domain:
 
     def sweep_bytes(self) -> float:
         return float(lib().lbmdem_sweep_bytes(self.h))
+
+
+class Batch:
+    """Many domains stepped together (one launch per kernel kind for all of
+    them, replayed from a captured HIP graph).  Domains must be created on
+    ``stream``."""
+
+    def __init__(self, stream, pool_bytes: int, use_graph: bool = True):
+        h = C.c_void_p()
+        rc = lib().lbmdem_batch_create(C.c_void_p(stream.cuda_stream), int(pool_bytes), C.byref(h))
+        if rc != OK:
+            raise LbmdemError(rc, "batch creation failed")
+        self.h = h
+        self.stream = stream
+        self.members = {}
+        if not use_graph:
+            self._check(lib().lbmdem_batch_set_graph(self.h, 0))
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LbmdemError(rc, lib().lbmdem_batch_last_error(self.h).decode())
+        return rc
+
+    def try_admit(self, dom) -> int | None:
+        """Slot id, or None when the pool budget is exhausted."""
+        slot = C.c_int32(-1)
+        rc = lib().lbmdem_batch_admit(self.h, dom.h, C.byref(slot))
+        if rc == ENOMEM:
+            return None
+        self._check(rc)
+        self.members[slot.value] = dom
+        return slot.value
+
+    def admit(self, dom) -> int:
+        slot = self.try_admit(dom)
+        if slot is None:
+            raise LbmdemError(ENOMEM, "pool budget exceeded")
+        return slot
+
+    def retire(self, slot: int):
+        dom = self.members.pop(slot)
+        self._check(lib().lbmdem_batch_retire(self.h, dom.h))
+        return dom
+
+    def step(self, n=1):
+        self._check(lib().lbmdem_batch_step(self.h, int(n)))
+
+    def status(self):
+        """{slot: (steps, stopped)} of the admitted domains."""
+        n = C.c_int32(max(len(self.members), 1))
+        sl = np.zeros(n.value, np.int32)
+        st = np.zeros(n.value, np.int64)
+        sp = np.zeros(n.value, np.int32)
+        self._check(lib().lbmdem_batch_status(self.h, sl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              st.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              sp.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+        return {int(sl[k]): (int(st[k]), bool(sp[k])) for k in range(n.value)}
+
+    def done(self) -> list[int]:
+        n = C.c_int32(max(len(self.members), 1))
+        sl = np.zeros(n.value, np.int32)
+        self._check(lib().lbmdem_batch_done(self.h, sl.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+        return [int(v) for v in sl[: n.value]]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbmdem_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_copy(dst_tensor, src_tensor, nbytes, stream):

@@ -15,6 +15,9 @@ Workloads:
                     density ratio U[2,8] and viscosity logU[0.005,0.05]
                     (rejecting u_s > 0.1), released from the ramp of
                     Eq. (artificial_acceleration) one diameter above the wall.
+  serve_requests  - a stream of independent sphere-wall requests with Poisson
+                    arrivals (edges, diameter, Stokes number, density ratio
+                    drawn per request), and serve_workload, the domain of one.
   dense           - cubic lattice with z walls, equal spheres placed by seeded
                     random sequential addition with a surface gap >= 1 to
                     every other sphere and wall (optionally smaller, and with
@@ -159,3 +162,51 @@ def dense(seed: int = 0, n: int = 96, count: int = 156, D: float = 12.0, rho_r: 
     return Workload("dense", p, x, np.full(count, R), np.full(count, rho_r), u,
                     np.zeros((count, 3)), steps,
                     meta=dict(seed=seed, solid_fraction=frac, min_gap=min_gap, u_rms=u_rms))
+
+
+def serve_requests(seed: int = 0, n: int = 512, rate: float = 50.0, edge_range=(48, 192),
+                   D_range=(6.0, 24.0), St_range=(1.0, 1000.0), rho_range=(1.5, 8.0), u_s: float = 0.02,
+                   nu_min: float = 1e-3) -> list[dict]:
+    """Requests of the serving mix: arrivals of a Poisson process of the given
+    rate (per second); edges uniform integers per axis with max/min <= 1.5,
+    L_z >= 6 D and min(L_x, L_y) >= 3 D; D uniform; St log-uniform (redrawn
+    while nu = u_s D rho_r / (9 St) < nu_min); rho_r uniform."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        while True:
+            L = rng.integers(edge_range[0], edge_range[1] + 1, size=3)
+            D = float(rng.uniform(*D_range))
+            if L.max() / L.min() <= 1.5 and L[2] >= 6 * D and min(L[0], L[1]) >= 3 * D:
+                break
+        rho_r = float(rng.uniform(*rho_range))
+        while True:
+            St = math.exp(rng.uniform(math.log(St_range[0]), math.log(St_range[1])))
+            nu = u_s * D * rho_r / (9.0 * St)
+            if nu >= nu_min:
+                break
+        jitter = rng.uniform(-0.5, 0.5, 2)
+        out.append(dict(id=k, arrival=t, L=tuple(int(v) for v in L), D=D, St=St, rho_r=rho_r, nu=nu,
+                        u_s=u_s, jitter=tuple(float(v) for v in jitter)))
+    return out
+
+
+def serve_workload(req: dict) -> Workload:
+    """Domain of one request: the sphere-wall protocol (ramp of
+    Eq. (artificial_acceleration) to u_s from 1.5 D below the top wall,
+    release one diameter above the bottom wall), gravity from the Froude
+    number of the St = 100 experiment, FP32-sized parameters."""
+    nx, ny, nz = req["L"]
+    D, u_s, nu, rho_r = req["D"], req["u_s"], req["nu"], req["rho_r"]
+    nu_phys = _ST100["mu_f"] / _ST100["rho_f"]
+    us_phys = 9.0 * 100.0 * nu_phys * _ST100["rho_f"] / (_ST100["rho_p"] * _ST100["D"])
+    fr = _ST100["g"] * _ST100["D"] / us_phys ** 2
+    g = fr * u_s ** 2 / D
+    x = np.array([nx / 2.0 + req["jitter"][0], ny / 2.0 + req["jitter"][1], (nz - 1.0) - 1.5 * D])
+    p = base_params(nx=nx, ny=ny, nz=nz, nu=nu, gravity=(0.0, 0.0, -g), max_spheres=1)
+    t_st = rho_r * D * D / (18.0 * nu)
+    ramp = dict(u_target=(0.0, 0.0, -u_s), c_acc=10.0, t_st=t_st, release_gap=D)
+    return Workload("serve", p, x[None], np.array([D / 2]), np.array([rho_r]), np.zeros((1, 3)),
+                    np.zeros((1, 3)), 0, ramp=ramp, meta=dict(req))

@@ -23,7 +23,7 @@ def oracle_domain(wl: W.Workload, **over):
     return d
 
 
-def gpu_domain(wl: W.Workload, storage=0, device="cuda:0", **over):
+def gpu_domain(wl: W.Workload, storage=0, device="cuda:0", stream=None, **over):
     from paper_2003_01490_amd import lbmdem as L
 
     p = dict(wl.params)
@@ -33,7 +33,7 @@ def gpu_domain(wl: W.Workload, storage=0, device="cuda:0", **over):
     p["storage"] = storage
     p["max_radius"] = float(max(wl.R)) if len(wl.R) else 1.0
     p["max_spheres"] = max(p.get("max_spheres", 1), len(wl.R), 1)
-    d = L.Domain(L.default_config(**p), device=device)
+    d = L.Domain(L.default_config(**p), device=device, stream=stream)
     if len(wl.R):
         d.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
     if wl.ramp is not None:
