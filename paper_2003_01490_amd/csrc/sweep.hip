@@ -3,9 +3,14 @@
 //
 // One thread per cell, one block per whole x-row group, so that the +-1
 // x-shifted loads of a row stay inside the block and every source value is
-// fetched from HBM once.  Solid and wall cells exit at once; their PDF slots
-// carry the boundary values of the links that stream out of them (written by
-// the boundary kernel), so every fluid cell pulls 19 values without branching.
+// fetched from HBM once.  The PDF slots of solid and wall cells carry the
+// boundary values of the links that stream out of them (written by the
+// boundary kernel), so every fluid cell pulls 19 values without branching.
+// Solid and wall cells are updated like fluid cells: their results are never
+// read (the boundary kernel rewrites every slot a fluid cell pulls from them),
+// and letting every lane load and store keeps each wavefront's accesses whole
+// cache lines (lanes that skipped their cell made partial-line writes, which
+// cost a quarter of the bandwidth in a 16 % solid suspension).
 //
 // Collision in deviation variables g = f - w_q:
 //   TRT in velocity space: g~_q = g_q - s+ (g+_q - e+_q) - s- (g-_q - e-_q),
@@ -58,7 +63,6 @@ __device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restr
   const unsigned int nxy = (unsigned int)nx * (unsigned int)ny;
   const unsigned int idx = (unsigned int)x + (unsigned int)nx * (unsigned int)y + nxy * (unsigned int)z;
   const uint8_t fl = flags[idx];
-  if (fl & (F_SOLID | F_WALL)) return;
 
   // source of direction q is x - c_q: index [1 - c] of these triples
   const unsigned int X0 = (unsigned int)(x == 0 ? nx - 1 : x - 1), X1 = (unsigned int)x,
@@ -192,7 +196,8 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
     block.x = d.nx;
     block.y = 256 / d.nx;
   } else {
-    const int cand[4] = {256, 192, 128, 64};
+    // 128 x 2 measured best for 384-wide rows
+    const int cand[4] = {128, 256, 192, 64};
     block.x = 256;
     for (int c : cand)
       if (d.nx % c == 0) {
