@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--max-steps", type=int, default=6000, help="serving stream: step cap per request")
     ap.add_argument("--chunk", type=int, default=100, help="serving stream: steps per batch call")
     ap.add_argument("--serve-baseline", action="store_true", help="serving stream: also run FIFO one at a time")
+    ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
+                    help="run the DEM beside the sweep on a second stream (1, default) or after it (0)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -279,6 +281,7 @@ def main():
     storage = {"f64": L.STORE_F64, "f32": L.STORE_F32, "f16": L.STORE_F16}[args.storage]
     wl = make_workload(args.workload, args.seed)
     cfg = _gpu_params(wl, storage)
+    cfg.overlap = args.overlap
     dev = torch.device("cuda:0")
     dom = L.Domain(cfg, device=dev)
     dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
@@ -344,6 +347,7 @@ def main():
             "n_sub": cfg.n_sub,
             "collision": "TRT+aB",
             "seed": args.seed,
+            "overlap": bool(args.overlap),
             "parallelism": "single GPU",
         },
         "roofline": {

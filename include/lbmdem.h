@@ -106,6 +106,13 @@ typedef struct lbmdem_config {
                                blocks per sphere (box slabs and row chunks), 2
                                one block per sphere (EINVAL if its LDS cube does
                                not fit); the force sums differ in rounding order */
+  int32_t overlap;          /* 1 (default): inside a step, the one-workgroup DEM
+                               kernels and the claims of the new positions run on
+                               a second, library-owned stream beside the sweep
+                               (they need only the previous step's forces); it
+                               waits on and rejoins the domain's stream within
+                               the step.  0: everything on the domain's stream.
+                               Results are identical.                             */
 } lbmdem_config;
 
 typedef struct lbmdem_domain lbmdem_domain;

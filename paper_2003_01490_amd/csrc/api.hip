@@ -176,6 +176,7 @@ const char* check_config(const lbmdem_config* c) {
   if (!(c->cut_n > 0.0 && c->cut_tt > 0.0 && c->cut_tr > 0.0)) return "cut-offs must be positive";
   if (c->dem_kernel < 0 || c->dem_kernel > 2) return "dem_kernel must be 0..2";
   if (c->map_kernel < 0 || c->map_kernel > 2) return "map_kernel must be 0..2";
+  if (c->overlap != 0 && c->overlap != 1) return "overlap must be 0 or 1";
   if (c->map_kernel == 2 && !ball_possible(*c))
     return "map_kernel 2 needs the staged cube (R_max + 4 cells each side) within 60000 bytes of LDS and "
            "within every periodic extent";
@@ -210,6 +211,10 @@ struct lbmdem_domain {
   int grid_cap = 0;                   // co-resident blocks of the grid-wide DEM kernel
   unsigned long long bar_base = 0;    // arrivals at the grid-wide barriers so far
   lbmdem_batch* batch = nullptr;      // batch the domain is admitted to
+  // second stream of an overlapped step (created on first use) and the events
+  // that fork it from and join it to the domain's stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 static int32_t fail(lbmdem_domain* dom, int32_t code, const std::string& msg) {
@@ -305,6 +310,7 @@ int32_t lbmdem_config_init(lbmdem_config* c) {
   c->max_radius = 12.0;
   c->dem_kernel = 0;
   c->map_kernel = 0;
+  c->overlap = 1;
   return LBMDEM_OK;
 }
 
@@ -458,6 +464,9 @@ int32_t lbmdem_destroy(lbmdem_domain* dom) {
   (void)hipStreamSynchronize(dom->stream);
   harvest(dom);
   for (auto e : dom->spare) (void)hipEventDestroy(e);
+  if (dom->side) (void)hipStreamDestroy(dom->side);
+  if (dom->ev_fork) (void)hipEventDestroy(dom->ev_fork);
+  if (dom->ev_join) (void)hipEventDestroy(dom->ev_join);
   if (dom->owns) (void)hipFree(dom->region);
   delete dom;
   return LBMDEM_OK;
@@ -617,26 +626,69 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, con
   return remap(dom, true);
 }
 
+// The DEM sub-cycles and the claims of step t need the forces formed by the
+// boundary pass of step t - 1 and the particle state, not the sweep of step
+// t, so with the one-workgroup DEM kernels they can run on a second stream
+// while the sweep runs.  (The grid-wide DEM kernel needs all its blocks
+// resident at once and stays on the domain's stream.)
+static bool overlap_step(const lbmdem_domain* dom) {
+  if (!dom->cfg.overlap || dom->d.P <= 0) return false;
+  const int k = dom->cfg.dem_kernel;
+  return !(k == 2 || (k == 0 && dom->d.P > DEM_GRID_MIN));
+}
+
+static int32_t ensure_side(lbmdem_domain* dom) {
+  if (dom->side) return LBMDEM_OK;
+  HIPCHK(dom, hipEventCreateWithFlags(&dom->ev_fork, hipEventDisableTiming));
+  HIPCHK(dom, hipEventCreateWithFlags(&dom->ev_join, hipEventDisableTiming));
+  HIPCHK(dom, hipStreamCreateWithFlags(&dom->side, hipStreamNonBlocking));
+  return LBMDEM_OK;
+}
+
 int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   if (!dom || nsteps < 0) return LBMDEM_EINVAL;
   if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
   if (dom->batch) return fail(dom, LBMDEM_EINVAL, "domain is stepped by its batch");
   dom->d.P = (int)dom->hR.size();
-  // One stream, back to back: the sweep (A -> B), the DEM sub-cycles and the
-  // claims of the new positions, then reconstruction and the boundary pass
-  // that commits the mapping and prepares the next step's links.
-  for (int s = 0; s < nsteps; ++s) {
-    timed(dom, 0, dom->stream, [&] { launch_sweep(dom->d, dom->stream); });
+  const bool ov = overlap_step(dom);
+  if (ov && nsteps > 0)
+    if (int32_t rc = ensure_side(dom)) return rc;
+  hipStream_t s = dom->stream;
+  // Per step: the sweep (A -> B) and, beside it or after it, the DEM
+  // sub-cycles and the claims of the new positions; then reconstruction, the
+  // boundary pass (mapping, boundary values and momentum-exchange partials of
+  // the next step, written into B) and the step control (B becomes current).
+  for (int k = 0; k < nsteps; ++k) {
     hipError_t e = hipSuccess;
-    timed(dom, 1, dom->stream, [&] {
-      e = launch_dem(dom->d, dom->cfg.dem_kernel, dom->grid_cap, &dom->bar_base, dom->stream);
-      launch_claim(dom->d, dom->stream);
-    });
+    hipStream_t ds = s;
+    if (ov) {
+      HIPCHK(dom, hipEventRecord(dom->ev_fork, s));
+      HIPCHK(dom, hipStreamWaitEvent(dom->side, dom->ev_fork, 0));
+      ds = dom->side;
+    }
+    auto dem = [&] {
+      timed(dom, 1, ds, [&] {
+        e = launch_dem(dom->d, dom->cfg.dem_kernel, dom->grid_cap, &dom->bar_base, ds);
+        launch_claim(dom->d, 1, ds);
+      });
+    };
+    if (!ov) {
+      timed(dom, 0, s, [&] { launch_sweep(dom->d, s); });
+      dem();
+    } else {
+      dem();
+      timed(dom, 0, s, [&] { launch_sweep(dom->d, s); });
+      HIPCHK(dom, hipEventRecord(dom->ev_join, ds));
+      HIPCHK(dom, hipStreamWaitEvent(s, dom->ev_join, 0));
+    }
     if (e != hipSuccess) {
       dom->failed = 1;
       return fail(dom, LBMDEM_EDEVICE, std::string("DEM launch failed: ") + hipGetErrorString(e));
     }
-    timed(dom, 2, dom->stream, [&] { launch_update(dom->d, true, dom->stream); });
+    timed(dom, 2, s, [&] {
+      launch_update(dom->d, true, 1, s);
+      launch_advance(dom->d, s);
+    });
   }
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;
@@ -1045,7 +1097,7 @@ static int32_t build_tables(lbmdem_batch* b) {
     const DevDomain& d = dom->d;
     ss[k + 1] = ss[k] + (int)((d.N + 255) / 256);
     cs[k + 1] = cs[k] + d.P * d.ZB;
-    ms[k + 1] = ms[k] + d.P * d.ZB * d.RB + (wall_cell_count(d) + 255) / 256;
+    ms[k + 1] = ms[k] + d.P * d.ZB * d.RB;
   }
   const size_t tb = align256(sizeof(DevDomain) * (size_t)std::max(nd, 1));
   const size_t ib = align256(4 * (size_t)(nd + 1));
@@ -1083,6 +1135,7 @@ static void launch_batch_step(lbmdem_batch* b) {
   launch_sweep_batch(b->t, b->stream);
   launch_dem_batch(b->t, b->stream);
   launch_mapping_batch(b->t, b->stream);
+  launch_advance_batch(b->t, b->stream);
 }
 
 extern "C" {

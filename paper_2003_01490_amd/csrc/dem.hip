@@ -453,20 +453,14 @@ __device__ __forceinline__ void dem_body(const DevDomain& d, const DevParticles&
 // ---- step control -----------------------------------------------------------
 
 // At the start of the step's DEM kernel: true if the domain does not step (it
-// is frozen, or the stop rule was met at the end of the last step, in which
-// case it freezes now).  Every thread may call it; one writes.
-__device__ __forceinline__ bool dem_stopped(const DevDomain& d, bool writer) {
-  if (d.ctl->frozen) return true;
-  if (d.ctl->stop_req) {
-    if (writer) d.ctl->frozen = 1;
-    return true;
-  }
-  return false;
-}
+// is frozen, or the stop rule was met at the end of the last step; the step
+// control kernel then freezes it).
+__device__ __forceinline__ bool dem_stopped(const DevDomain& d) { return !step_live(d.ctl); }
 
-// At the end of the step's DEM work, by one thread: count the step, flip the
-// current PDF buffer (the sweep has written the other one), take a new mapping
-// stamp for the claims of the new positions, and evaluate the stop rule.  The
+// At the end of the step, by one thread, after the sweep, the DEM and the
+// mapping update: count the step, flip the current PDF buffer (the sweep has
+// written the other one, the mapping update completed it), move the mapping
+// stamp to the claims of the new positions, and evaluate the stop rule.  The
 // rebound rule follows sphere 0: approach, wall or sphere contact (collision
 // force of the last sub-cycle non-zero), contact over, rising (u_z > 0), apex
 // (u_z <= 0 again).
@@ -493,21 +487,34 @@ __device__ __forceinline__ void advance_step(const DevDomain& d, const DevPartic
   if (stop) c->stop_req = 1;
 }
 
-// the step without spheres: control only
-__global__ void k_step_ctl(DevDomain d) {
-  if (dem_stopped(d, true)) return;
+// Step control, one thread: a domain whose stop rule was met at the end of
+// the last step (and which therefore skipped this step) freezes; otherwise
+// the step is completed.
+__device__ __forceinline__ void step_control(const DevDomain& d) {
+  DevCtl* c = d.ctl;
+  if (c->frozen) return;
+  if (c->stop_req) {
+    c->frozen = 1;
+    return;
+  }
   advance_step(d, d.p);
+}
+
+__global__ void k_advance(DevDomain d) { step_control(d); }
+
+__global__ void k_advance_batch(const DevDomain* __restrict__ tab, int ndom) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ndom) step_control(tab[k]);
 }
 
 // one workgroup, state in global memory
 __device__ __forceinline__ void dem_global_run(const DevDomain& d) {
   dem_body(d, d.p);
-  __syncthreads();
-  if (threadIdx.x == 0) advance_step(d, d.p);
 }
 
 __global__ __launch_bounds__(256) void k_dem(DevDomain d) {
-  if (dem_stopped(d, threadIdx.x == 0)) return;
+  __builtin_amdgcn_s_setprio(3);
+  if (dem_stopped(d)) return;
   dem_global_run(d);
 }
 
@@ -515,8 +522,6 @@ __global__ __launch_bounds__(256) void k_dem(DevDomain d) {
 // for the whole step, so the sub-cycles (separated by workgroup barriers) do
 // not wait on memory round trips.
 constexpr int DEM_LDS_MAX = 32;
-// automatic choice: above this many spheres the grid-wide kernel
-constexpr int DEM_GRID_MIN = 256;
 
 __device__ __forceinline__ void dem_lds_run(const DevDomain& d) {
   constexpr int PS = DEM_LDS_MAX;
@@ -590,19 +595,21 @@ __device__ __forceinline__ void dem_lds_run(const DevDomain& d) {
       for (int a = 0; a < 3; ++a) g.hist_d[3 * ((size_t)HIST_SLOTS * t + k) + a] = shd[3 * (HIST_SLOTS * t + k) + a];
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) advance_step(d, g);
 }
 
+// The one-workgroup kernels run beside the sweep in an overlapped step: they
+// are a chain of dependent FP64 work, so their waves take the highest issue
+// priority on the CUs they share with the sweep's waves.
 __global__ __launch_bounds__(256) void k_dem_lds(DevDomain d) {
-  if (dem_stopped(d, threadIdx.x == 0)) return;
+  __builtin_amdgcn_s_setprio(3);
+  if (dem_stopped(d)) return;
   dem_lds_run(d);
 }
 
 // many domains, one workgroup each (the few-sphere kernels above)
 __global__ __launch_bounds__(256) void k_dem_batch(const DevDomain* __restrict__ tab, int ndom) {
   const DevDomain& d = tab[blockIdx.x];
-  if (dem_stopped(d, threadIdx.x == 0)) return;
+  if (dem_stopped(d)) return;
   if (d.P <= DEM_LDS_MAX)
     dem_lds_run(d);
   else
@@ -611,6 +618,12 @@ __global__ __launch_bounds__(256) void k_dem_batch(const DevDomain* __restrict__
 
 void launch_dem_batch(const BatchTables& b, hipStream_t s) {
   if (b.ndom > 0) hipLaunchKernelGGL(k_dem_batch, dim3(b.ndom), dim3(256), 0, s, b.tab, b.ndom);
+}
+
+void launch_advance(const DevDomain& d, hipStream_t s) { hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, d); }
+
+void launch_advance_batch(const BatchTables& b, hipStream_t s) {
+  if (b.ndom > 0) hipLaunchKernelGGL(k_advance_batch, dim3((b.ndom + 63) / 64), dim3(64), 0, s, b.tab, b.ndom);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,7 +749,7 @@ __host__ __device__ inline unsigned long long grid_barriers(const DevDomain& d) 
 }
 
 __global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsigned long long base) {
-  if (dem_stopped(d, blockIdx.x == 0 && threadIdx.x == 0)) {
+  if (dem_stopped(d)) {
     // keep the arrival count what the host expects for this launch
     if (threadIdx.x == 0) atomicAdd(d.barrier, grid_barriers(d));
     return;
@@ -797,8 +810,6 @@ __global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsi
       }
     health_check(d, p, i);
   }
-  // sphere 0 was advanced by this very thread
-  if (blockIdx.x == 0 && threadIdx.x == 0) advance_step(d, p);
 }
 
 int dem_grid_capacity() {
@@ -813,10 +824,7 @@ int dem_grid_capacity() {
 
 hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
                       hipStream_t s) {
-  if (d.P <= 0) {
-    hipLaunchKernelGGL(k_step_ctl, dim3(1), dim3(1), 0, s, d);
-    return hipGetLastError();
-  }
+  if (d.P <= 0) return hipSuccess;
   const bool grid = kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN);
   if (!grid) {
     if (d.P <= DEM_LDS_MAX)

@@ -72,6 +72,10 @@ struct DevCtl {
   int32_t rb_phase;   // rebound tracking: 0 approach, 1 contact, 2 after contact, 3 rising
 };
 
+// A step's kernels do nothing for a domain that is frozen or whose stop rule
+// was met at the end of the last step.
+__device__ __forceinline__ bool step_live(const DevCtl* c) { return !c->frozen && !c->stop_req; }
+
 constexpr int STOP_NONE = 0;
 constexpr int STOP_REBOUND = 1;
 
@@ -175,7 +179,7 @@ struct BatchTables {
   const DevDomain* tab;
   const int* sweep_start;
   const int* claim_start;   // P * ZB blocks per domain (claims, reconstruction)
-  const int* commit_start;  // P * ZB * RB sphere blocks + wall blocks per domain
+  const int* commit_start;  // P * ZB * RB sphere blocks per domain
   int ndom;
   int sweep_blocks, claim_blocks, commit_blocks;
   int storage;
@@ -194,24 +198,20 @@ __device__ __forceinline__ int batch_domain(const int* start, int ndom, int b) {
   return lo;
 }
 
-// cells of the wall layers (boundary values of moving-wall bounce-back)
-__host__ __device__ inline int wall_cell_count(const DevDomain& d) {
-  int n = 0;
-  const int nzi = d.nz - 2 * d.walls[2], nyi = d.ny - 2 * d.walls[1];
-  if (d.walls[2]) n += 2 * d.nx * d.ny;
-  if (d.walls[1]) n += 2 * d.nx * nzi;
-  if (d.walls[0]) n += 2 * nyi * nzi;
-  return n;
-}
-
 // host-side launchers (implemented in the .hip files)
 void launch_sweep(const DevDomain& d, hipStream_t s);
-// a new mapping stamp, then claim + (reconstruction) + commit/boundary values,
-// in order on one stream (mapping updates outside the step)
+// mapping update outside the step: claim + (reconstruction) + commit/boundary
+// values on the current buffer, then the new stamp, in order on one stream
 void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s);
-// the claim kernel alone (needs only the particle positions), and the rest
-void launch_claim(const DevDomain& d, hipStream_t s);
-void launch_update(const DevDomain& d, bool reconstruct, hipStream_t s);
+// the claim kernel alone (needs only the particle positions), and the rest;
+// in_step = 1 inside a step (after the sweep and the DEM, before the step
+// control), 0 for an update outside the step
+void launch_claim(const DevDomain& d, int in_step, hipStream_t s);
+void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s);
+// step control (last kernel of a step): freeze, or count the step, flip the
+// buffers, move the stamp and evaluate the stop rule
+void launch_advance(const DevDomain& d, hipStream_t s);
+void launch_advance_batch(const BatchTables& b, hipStream_t s);
 // DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 grid-wide
 // (cooperative).  *barrier_base is the arrival count the grid barriers start
 // from; it is advanced by the arrivals of the launch.
@@ -221,6 +221,8 @@ hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned lon
 // co-resident blocks of the grid-wide DEM kernel on the current device
 int dem_grid_capacity();
 constexpr int DEM_GRID_THREADS = 128;
+// automatic DEM kernel choice: above this many spheres the grid-wide kernel
+constexpr int DEM_GRID_MIN = 256;
 void launch_fields(const DevDomain& d, int field, double* dst, hipStream_t s);
 void launch_set_pdf(const DevDomain& d, int q, const double* src, hipStream_t s);
 void launch_fill_claims(const DevDomain& d, hipStream_t s);

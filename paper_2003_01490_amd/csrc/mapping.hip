@@ -21,8 +21,12 @@
 //              reduced per block in a fixed order (no atomics) into
 //              partial[i][b].  Links from y to a wall or to another sphere's
 //              solid are missing links: F_q = 2 w_q c_q with arm y - c_q/2.
-//              Extra blocks write the moving-wall bounce-back values into the
-//              wall-cell slots.
+// Inside a step the three kernels run after the sweep and the DEM, before the
+// step control advances the domain: they claim with the next mapping stamp
+// and work on the buffer the sweep has just written (the next current one).
+// A mapping update outside the step (new or moved spheres) works on the
+// current buffer, then takes the new stamp.  (Moving-wall bounce-back is done
+// by the sweep itself.)
 // The squared distances are formed as (dx*dx + dy*dy) + dz*dz in FP64 without
 // contraction, so that the flags are a deterministic function of the FP64
 // positions.
@@ -156,12 +160,23 @@ __device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_
   })
 }
 
-__global__ __launch_bounds__(256) void k_claim(DevDomain d) {
-  if (d.ctl->frozen) return;
-  claim_block(d, blockIdx.x, d.ctl->stamp);
+// Whether a mapping kernel runs, which buffer it works on and its stamp:
+// inside a step (in_step = 1) the domain must be live and the buffer is the
+// one the sweep wrote; outside, only a frozen domain is skipped.  The claims
+// always carry the next stamp.
+__device__ __forceinline__ bool map_live(const DevCtl* c, int in_step) {
+  return in_step ? step_live(c) : !c->frozen;
+}
+__device__ __forceinline__ int map_buffer(const DevCtl* c, int in_step) { return c->cur ^ (in_step ? 1 : 0); }
+__device__ __forceinline__ uint32_t map_stamp(const DevCtl* c) { return c->stamp + 1u; }
+
+__global__ __launch_bounds__(256) void k_claim(DevDomain d, int in_step) {
+  __builtin_amdgcn_s_setprio(3);  // runs beside the sweep in an overlapped step
+  if (!map_live(d.ctl, in_step)) return;
+  claim_block(d, blockIdx.x, map_stamp(d.ctl));
 }
 
-// a new mapping stamp (mapping updates outside the step)
+// the new stamp after a mapping update outside the step
 __global__ void k_new_stamp(DevCtl* ctl) { ctl->stamp += 1; }
 
 // Eq. (PDF_reconstruction) for cell (ii,jj,kk) formerly covered by sphere i
@@ -376,9 +391,9 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_recon(DevDomain d) {
-  if (d.ctl->frozen) return;
-  recon_block<T>(d, blockIdx.x, d.ctl->cur, d.ctl->stamp);
+__global__ __launch_bounds__(256) void k_recon(DevDomain d, int in_step) {
+  if (!map_live(d.ctl, in_step)) return;
+  recon_block<T>(d, blockIdx.x, map_buffer(d.ctl, in_step), map_stamp(d.ctl));
 }
 
 // smallest root in [0,1] of |r + delta c|^2 = R^2 (x_b = x + delta_q c_q)
@@ -495,86 +510,10 @@ __device__ inline void link_batch(const LinkCtx<T>& c, double* acc) {
   }
 }
 
-// Moving-wall bounce-back into the slots of wall cell number t (of nwall):
-// slot (y, q) receives f~_qbar(x) + 6 w_q (u_w . c_q) for the fluid cell
-// x = y + c_q.
 template <typename T>
-__device__ __forceinline__ void wall_cell_values(const DevDomain& d, T* buf, uint32_t stamp, int t, int nwall) {
-  const size_t N = (size_t)d.N;
-  if (t >= nwall) return;
-  int rem = t, ii = 0, jj = 0, kk = 0;
-  const int wz = d.walls[2], wy = d.walls[1];
-  const int nyi = d.ny - 2 * wy, nzi = d.nz - 2 * wz;
-  if (wz && rem < 2 * d.nx * d.ny) {
-    kk = rem < d.nx * d.ny ? 0 : d.nz - 1;
-    rem %= d.nx * d.ny;
-    ii = rem % d.nx;
-    jj = rem / d.nx;
-  } else {
-    if (wz) rem -= 2 * d.nx * d.ny;
-    if (wy && rem < 2 * d.nx * nzi) {
-      jj = rem < d.nx * nzi ? 0 : d.ny - 1;
-      rem %= d.nx * nzi;
-      ii = rem % d.nx;
-      kk = rem / d.nx + wz;
-    } else {
-      if (wy) rem -= 2 * d.nx * nzi;
-      ii = rem < nyi * nzi ? 0 : d.nx - 1;
-      rem %= nyi * nzi;
-      jj = rem % nyi + wy;
-      kk = rem / nyi + wz;
-    }
-  }
-  double uw[3] = {0, 0, 0};
-  if (wz && kk == 0) {
-    uw[0] = d.wall_u_lo[0];
-    uw[1] = d.wall_u_lo[1];
-    uw[2] = d.wall_u_lo[2];
-  } else if (wz && kk == d.nz - 1) {
-    uw[0] = d.wall_u_hi[0];
-    uw[1] = d.wall_u_hi[1];
-    uw[2] = d.wall_u_hi[2];
-  }
-  const long long y = cidx(d, ii, jj, kk);
-  // all neighbour states first, then the PDFs of the fluid ones, then the
-  // stores: two memory round trips per wall cell instead of one per direction
-  bool ok[Q];
-  long long xs[Q];
-  uint8_t sfl[Q];
-  unsigned long long sk[Q];
-#pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    int xi = ii + CX[q], xj = jj + CY[q], xk = kk + CZ[q];
-    ok[q] = !((d.walls[0] && (xi < 0 || xi >= d.nx)) || (d.walls[1] && (xj < 0 || xj >= d.ny)) ||
-              (d.walls[2] && (xk < 0 || xk >= d.nz)));
-    xs[q] = cidx(d, wrapi(xi, d.nx), wrapi(xj, d.ny), wrapi(xk, d.nz));
-    if (ok[q]) {
-      sfl[q] = d.flags[xs[q]];
-      sk[q] = d.claim[xs[q]];
-    }
-  }
-  double v[Q];
-#pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    // fluid after this update: not a wall, not claimed by this stamp
-    ok[q] = ok[q] && !(sfl[q] & F_WALL) && (uint32_t)(sk[q] >> 32) != stamp;
-    if (ok[q]) v[q] = ldv<T>(buf + (size_t)OPP[q] * N + xs[q]);
-  }
-#pragma unroll
-  for (int q = 1; q < Q; ++q)
-    if (ok[q])
-      stv<T>(buf + (size_t)q * N + y, v[q] + 6.0 * WQ[q] * (uw[0] * CX[q] + uw[1] * CY[q] + uw[2] * CZ[q]));
-}
-
-template <typename T>
-__device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cur, uint32_t stamp, int nwall) {
-  const int nsb = d.P * d.ZB * d.RB;
+__device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cur, uint32_t stamp) {
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
-  if (blk >= nsb) {
-    wall_cell_values<T>(d, buf, stamp, (blk - nsb) * blockDim.x + threadIdx.x, nwall);
-    return;
-  }
   const int nbs = d.ZB * d.RB;
   const int i = blk / nbs, b = blk % nbs;
   const int bz = b / d.RB, brow = b % d.RB;
@@ -691,9 +630,9 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit(DevDomain d, int nwall) {
-  if (d.ctl->frozen) return;
-  commit_block<T>(d, blockIdx.x, d.ctl->cur, d.ctl->stamp, nwall);
+__global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step) {
+  if (!map_live(d.ctl, in_step)) return;
+  commit_block<T>(d, blockIdx.x, map_buffer(d.ctl, in_step), map_stamp(d.ctl));
 }
 
 // Many spheres: one block per sphere.  The states of all cells within R + 3 of
@@ -706,17 +645,13 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int nwall) {
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int nwall) {
-  if (d.ctl->frozen) return;
-  const int cur = d.ctl->cur;
-  const uint32_t stamp = d.ctl->stamp;
+__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int in_step) {
+  if (!map_live(d.ctl, in_step)) return;
+  const int cur = map_buffer(d.ctl, in_step);
+  const uint32_t stamp = map_stamp(d.ctl);
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
-  const int P = d.P;
-  if ((int)blockIdx.x >= P) {
-    wall_cell_values<T>(d, buf, stamp, (blockIdx.x - P) * blockDim.x + threadIdx.x, nwall);
-    return;
-  }
+  if ((int)blockIdx.x >= d.P) return;
   extern __shared__ uint8_t smem[];
   const int he = d.stage_edge, H = he / 2;
   const int NS = he * he * he;
@@ -888,41 +823,38 @@ __global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int nwall) {
 }
 
 
-void launch_claim(const DevDomain& d, hipStream_t s) {
+void launch_claim(const DevDomain& d, int in_step, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d);
+  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, in_step);
 }
 
 template <typename T>
-static void launch_update_t(const DevDomain& d, bool reconstruct, hipStream_t s) {
+static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0 && reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d);
-  const int nwall = wall_cell_count(d);
-  const int wblocks = (nwall + 255) / 256;
+  if (nsb <= 0) return;
+  if (reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, in_step);
   if (d.map_ball) {
     const size_t lds = (((size_t)d.stage_edge * d.stage_edge * d.stage_edge + 15) & ~(size_t)15) +
                        2 * (size_t)d.list_cap;
-    if (d.P + wblocks > 0)
-      hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P + wblocks), dim3(256), lds, s, d, nwall);
+    hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P), dim3(256), lds, s, d, in_step);
     return;
   }
-  const int ncb = nsb * d.RB;
-  if (ncb + wblocks > 0) hipLaunchKernelGGL(k_commit<T>, dim3(ncb + wblocks), dim3(256), 0, s, d, nwall);
+  hipLaunchKernelGGL(k_commit<T>, dim3(nsb * d.RB), dim3(256), 0, s, d, in_step);
 }
 
-void launch_update(const DevDomain& d, bool reconstruct, hipStream_t s) {
+void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s) {
   if (d.storage == 0)
-    launch_update_t<double>(d, reconstruct, s);
+    launch_update_t<double>(d, reconstruct, in_step, s);
   else if (d.storage == 1)
-    launch_update_t<float>(d, reconstruct, s);
+    launch_update_t<float>(d, reconstruct, in_step, s);
   else
-    launch_update_t<__half>(d, reconstruct, s);
+    launch_update_t<__half>(d, reconstruct, in_step, s);
 }
 
 void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
+  launch_claim(d, 0, s);
+  launch_update(d, reconstruct, 0, s);
   hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
-  launch_claim(d, s);
-  launch_update(d, reconstruct, s);
 }
 
 // ---- batched mapping update (slab blocks; one launch per kernel for all domains)
@@ -931,8 +863,8 @@ __global__ __launch_bounds__(256) void k_claim_batch(const DevDomain* __restrict
                                                      int ndom) {
   const int k = batch_domain(start, ndom, (int)blockIdx.x);
   const DevDomain& d = tab[k];
-  if (d.ctl->frozen) return;
-  claim_block(d, (int)blockIdx.x - start[k], d.ctl->stamp);
+  if (!step_live(d.ctl)) return;
+  claim_block(d, (int)blockIdx.x - start[k], map_stamp(d.ctl));
 }
 
 template <typename T>
@@ -940,8 +872,8 @@ __global__ __launch_bounds__(256) void k_recon_batch(const DevDomain* __restrict
                                                      int ndom) {
   const int k = batch_domain(start, ndom, (int)blockIdx.x);
   const DevDomain& d = tab[k];
-  if (d.ctl->frozen) return;
-  recon_block<T>(d, (int)blockIdx.x - start[k], d.ctl->cur, d.ctl->stamp);
+  if (!step_live(d.ctl)) return;
+  recon_block<T>(d, (int)blockIdx.x - start[k], map_buffer(d.ctl, 1), map_stamp(d.ctl));
 }
 
 template <typename T>
@@ -949,8 +881,8 @@ __global__ __launch_bounds__(256) void k_commit_batch(const DevDomain* __restric
                                                       int ndom) {
   const int k = batch_domain(start, ndom, (int)blockIdx.x);
   const DevDomain& d = tab[k];
-  if (d.ctl->frozen) return;
-  commit_block<T>(d, (int)blockIdx.x - start[k], d.ctl->cur, d.ctl->stamp, wall_cell_count(d));
+  if (!step_live(d.ctl)) return;
+  commit_block<T>(d, (int)blockIdx.x - start[k], map_buffer(d.ctl, 1), map_stamp(d.ctl));
 }
 
 template <typename T>

@@ -3,14 +3,19 @@
 //
 // One thread per cell, one block per whole x-row group, so that the +-1
 // x-shifted loads of a row stay inside the block and every source value is
-// fetched from HBM once.  The PDF slots of solid and wall cells carry the
-// boundary values of the links that stream out of them (written by the
-// boundary kernel), so every fluid cell pulls 19 values without branching.
+// fetched from HBM once.  The PDF slots of solid cells carry the boundary
+// values of the particle links that stream out of them (written by the
+// boundary kernel), so a fluid cell pulls 19 values without branching.  Wall
+// layers are fixed, so the sweep knows from the cell's coordinates which
+// values come from a wall: a cell next to a wall layer replaces them by the
+// moving-wall bounce-back value f~_qbar(x) + 6 w_q (u_w . c_q) of Sec. 2.2
+// (half-way walls), formed from its own post-collision values.  For z walls
+// that is a branch uniform over a block (a block lies in one z plane).
 // Solid and wall cells are updated like fluid cells: their results are never
-// read (the boundary kernel rewrites every slot a fluid cell pulls from them),
-// and letting every lane load and store keeps each wavefront's accesses whole
-// cache lines (lanes that skipped their cell made partial-line writes, which
-// cost a quarter of the bandwidth in a 16 % solid suspension).
+// read (the boundary kernel rewrites every slot a fluid cell pulls from a
+// solid cell), and letting every lane load and store keeps each wavefront's
+// accesses whole cache lines (lanes that skipped their cell made partial-line
+// writes, which cost a quarter of the bandwidth in a 16 % solid suspension).
 //
 // Collision in deviation variables g = f - w_q:
 //   TRT in velocity space: g~_q = g_q - s+ (g+_q - e+_q) - s- (g-_q - e-_q),
@@ -52,17 +57,49 @@ struct Store<__half> {
   }
 };
 
+// directions q whose source x - c_q lies across a wall layer, per side
+constexpr unsigned int DIR_XP = (1u << 4) | (1u << 8) | (1u << 10) | (1u << 14) | (1u << 18);  // c_x = +1
+constexpr unsigned int DIR_XM = (1u << 3) | (1u << 7) | (1u << 9) | (1u << 13) | (1u << 17);   // c_x = -1
+constexpr unsigned int DIR_YP = (1u << 1) | (1u << 7) | (1u << 8) | (1u << 11) | (1u << 15);   // c_y = +1
+constexpr unsigned int DIR_YM = (1u << 2) | (1u << 9) | (1u << 10) | (1u << 12) | (1u << 16);  // c_y = -1
+constexpr unsigned int DIR_ZP = (1u << 5) | (1u << 11) | (1u << 12) | (1u << 13) | (1u << 14); // c_z = +1
+constexpr unsigned int DIR_ZM = (1u << 6) | (1u << 15) | (1u << 16) | (1u << 17) | (1u << 18); // c_z = -1
+
+// Moving-wall bounce-back for the directions in mask wm: the value pulled from
+// the wall cell x - c_q becomes f~_qbar(x) + 6 w_q (u_w . c_q) (deviations:
+// the weights cancel).  Only the z wall layers move (the layer z = 0 with
+// wall_u_lo, z = nz - 1 with wall_u_hi; edge cells belong to the z layers).
 template <typename T>
-__device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restrict__ dst,
-                                           const uint8_t* __restrict__ flags, int x, int y, int z,
-                                           int nx, int ny, int nz, unsigned int N,
-                                           typename Store<T>::C sp, typename Store<T>::C sm,
-                                           typename Store<T>::C db_shell,
+__device__ __forceinline__ void wall_values(const DevDomain& d, const T* __restrict__ src, size_t NN,
+                                         unsigned int idx, int z, unsigned int wm,
+                                         typename Store<T>::C* g) {
+  using C = typename Store<T>::C;
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    if (!((wm >> q) & 1u)) continue;
+    double uc = 0.0;
+    if (d.walls[2]) {
+      const int zs = z - CZ[q];
+      if (zs == 0)
+        uc = d.wall_u_lo[0] * CX[q] + d.wall_u_lo[1] * CY[q] + d.wall_u_lo[2] * CZ[q];
+      else if (zs == d.nz - 1)
+        uc = d.wall_u_hi[0] * CX[q] + d.wall_u_hi[1] * CY[q] + d.wall_u_hi[2] * CZ[q];
+    }
+    const double v = (double)Store<T>::load(src + (size_t)OPP[q] * NN + idx);
+    g[q] = (C)(v + 6.0 * WQ[q] * uc);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restrict__ src, T* __restrict__ dst,
+                                           int x, int y, int z, typename Store<T>::C sp,
+                                           typename Store<T>::C sm, typename Store<T>::C db_shell,
                                            typename Store<T>::C db_other) {
   using C = typename Store<T>::C;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
   const unsigned int nxy = (unsigned int)nx * (unsigned int)ny;
   const unsigned int idx = (unsigned int)x + (unsigned int)nx * (unsigned int)y + nxy * (unsigned int)z;
-  const uint8_t fl = flags[idx];
+  const uint8_t fl = d.flags[idx];
 
   // source of direction q is x - c_q: index [1 - c] of these triples
   const unsigned int X0 = (unsigned int)(x == 0 ? nx - 1 : x - 1), X1 = (unsigned int)x,
@@ -73,7 +110,7 @@ __device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restr
   const unsigned int Z0 = (unsigned int)(z == 0 ? nz - 1 : z - 1) * nxy, Z1 = (unsigned int)z * nxy,
                      Z2 = (unsigned int)(z == nz - 1 ? 0 : z + 1) * nxy;
 
-  const size_t NN = (size_t)N;
+  const size_t NN = (size_t)d.N;
 #define LD(q, xs, ys, zs) Store<T>::load(src + (size_t)(q) * NN + (xs + ys + zs))
   C g[Q];
   g[0] = LD(0, X1, Y1, Z1);
@@ -96,6 +133,12 @@ __device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restr
   g[17] = LD(17, X2, Y1, Z2);  // c = (-1, 0,-1)
   g[18] = LD(18, X0, Y1, Z2);  // c = ( 1, 0,-1)
 #undef LD
+
+  unsigned int wm = 0u;
+  if (d.walls[2]) wm |= (z == 1 ? DIR_ZP : 0u) | (z == nz - 2 ? DIR_ZM : 0u);
+  if (d.walls[1]) wm |= (y == 1 ? DIR_YP : 0u) | (y == ny - 2 ? DIR_YM : 0u);
+  if (d.walls[0]) wm |= (x == 1 ? DIR_XP : 0u) | (x == nx - 2 ? DIR_XM : 0u);
+  if (wm) wall_values<T>(d, src, NN, idx, z, wm, g);
 
   // moments (rho0 = 1: u = j; deviations carry no mass or momentum of w_q)
   const C sumd = ((g[7] + g[8]) + (g[9] + g[10])) + ((g[11] + g[12]) + (g[13] + g[14])) +
@@ -154,19 +197,19 @@ __device__ __forceinline__ void sweep_cell(const T* __restrict__ src, T* __restr
 // one domain: whole x-rows per block (see launch_sweep_t); the current buffer
 // is read from the domain's step state
 template <typename T>
-__global__ __launch_bounds__(256) void k_sweep(T* __restrict__ pa, T* __restrict__ pb,
-                                               const uint8_t* __restrict__ flags, const DevCtl* ctl,
-                                               int nx, int ny, int nz, unsigned int N,
-                                               typename Store<T>::C sp, typename Store<T>::C sm,
-                                               typename Store<T>::C db_shell,
-                                               typename Store<T>::C db_other) {
-  if (ctl->frozen) return;
-  const int cur = ctl->cur;
+__global__ __launch_bounds__(256) void k_sweep(DevDomain d) {
+  using C = typename Store<T>::C;
+  if (!step_live(d.ctl)) return;
+  const int cur = d.ctl->cur;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= nx || y >= ny) return;
-  sweep_cell<T>(cur ? pb : pa, cur ? pa : pb, flags, x, y, blockIdx.z, nx, ny, nz, N, sp, sm, db_shell,
-                db_other);
+  if (x >= d.nx || y >= d.ny) return;
+  // (selects, not an index: a run-time index into the by-value argument would
+  // place the whole descriptor in scratch memory)
+  const T* src = (const T*)(cur ? d.pdf[1] : d.pdf[0]);
+  T* dst = (T*)(cur ? d.pdf[0] : d.pdf[1]);
+  sweep_cell<T>(d, src, dst, x, y, blockIdx.z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
+                (C)(d.s_bulk_other - d.s_plus));
 }
 
 // many domains in one launch: block b belongs to the domain k with
@@ -177,15 +220,15 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const DevDomain* __restrict
   using C = typename Store<T>::C;
   const int k = batch_domain(start, ndom, (int)blockIdx.x);
   const DevDomain& d = tab[k];
-  if (d.ctl->frozen) return;
+  if (!step_live(d.ctl)) return;
   const long long c = (long long)(blockIdx.x - start[k]) * 256 + threadIdx.x;
   if (c >= d.N) return;
   const int x = (int)(c % d.nx), y = (int)((c / d.nx) % d.ny), z = (int)(c / ((long long)d.nx * d.ny));
   const int cur = d.ctl->cur;
-  T* pa = (T*)d.pdf[0];
-  T* pb = (T*)d.pdf[1];
-  sweep_cell<T>(cur ? pb : pa, cur ? pa : pb, d.flags, x, y, z, d.nx, d.ny, d.nz, (unsigned int)d.N,
-                (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
+  const T* src = (const T*)d.pdf[cur];
+  T* dst = (T*)d.pdf[cur ^ 1];
+  sweep_cell<T>(d, src, dst, x, y, z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
+                (C)(d.s_bulk_other - d.s_plus));
 }
 
 template <typename T>
@@ -210,10 +253,7 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
   grid.x = (d.nx + block.x - 1) / block.x;
   grid.y = (d.ny + block.y - 1) / block.y;
   grid.z = d.nz;
-  using C = typename Store<T>::C;
-  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, (T*)d.pdf[0], (T*)d.pdf[1], (const uint8_t*)d.flags,
-                     (const DevCtl*)d.ctl, d.nx, d.ny, d.nz, (unsigned int)d.N, (C)d.s_plus,
-                     (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
+  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, d);
 }
 
 void launch_sweep(const DevDomain& d, hipStream_t s) {

@@ -50,6 +50,7 @@ class Config(C.Structure):
         ("max_radius", C.c_double),
         ("dem_kernel", C.c_int32),
         ("map_kernel", C.c_int32),
+        ("overlap", C.c_int32),
     ]
 
 

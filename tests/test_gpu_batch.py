@@ -45,6 +45,34 @@ def _same(a, b):
     return all(np.array_equal(x, y) for x, y in zip(_bits(a), _bits(b)))
 
 
+@pytest.mark.parametrize("case", ["requests", "agitated"])
+def test_overlap_equals_sequential(case):
+    """The DEM and the claims beside the sweep on a second stream give the
+    same bits as the whole step on one stream (one-workgroup DEM kernels:
+    with state in LDS up to 32 spheres, in global memory above)."""
+    import torch
+
+    from paper_2003_01490_amd import lbmdem as L
+
+    stream = torch.cuda.Stream()
+    if case == "requests":
+        wls, steps = _requests(7, 3), 150
+    else:
+        wls, steps = [W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)], 60
+    _case(f"overlap vs sequential, {case}: " + ", ".join(
+        f"{w.params['nx']}x{w.params['ny']}x{w.params['nz']} P={len(w.R)}" for w in wls))
+    for w in wls:
+        a = _make(w, stream, overlap=1)
+        b = _make(w, stream, overlap=0)
+        for _ in range(3):
+            a.step(steps // 3)
+            b.step(steps // 3)
+        assert a.progress() == b.progress() == (steps // 3 * 3, False)
+        assert _same(a, b), "overlapped step differs from the sequential one"
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_batch_equals_alone(use_graph):
     import torch
