@@ -57,38 +57,40 @@ struct Store<__half> {
   }
 };
 
-// directions q whose source x - c_q lies across a wall layer, per side
-constexpr unsigned int DIR_XP = (1u << 4) | (1u << 8) | (1u << 10) | (1u << 14) | (1u << 18);  // c_x = +1
-constexpr unsigned int DIR_XM = (1u << 3) | (1u << 7) | (1u << 9) | (1u << 13) | (1u << 17);   // c_x = -1
-constexpr unsigned int DIR_YP = (1u << 1) | (1u << 7) | (1u << 8) | (1u << 11) | (1u << 15);   // c_y = +1
-constexpr unsigned int DIR_YM = (1u << 2) | (1u << 9) | (1u << 10) | (1u << 12) | (1u << 16);  // c_y = -1
-constexpr unsigned int DIR_ZP = (1u << 5) | (1u << 11) | (1u << 12) | (1u << 13) | (1u << 14); // c_z = +1
-constexpr unsigned int DIR_ZM = (1u << 6) | (1u << 15) | (1u << 16) | (1u << 17) | (1u << 18); // c_z = -1
+// Moving-wall bounce-back of direction q (c = (cx, cy, cz), weight w, opposite
+// qb): the value pulled from the wall cell x - c_q becomes
+// f~_qb(x) + 6 w (u_w . c_q); in deviations the weights cancel.
+#define WALL_BB(q, qb, w, cx, cy, cz, ux, uy, uz)                                         \
+  g[q] = (C)((double)Store<T>::load(src + (size_t)(qb) * NN + idx) +                       \
+             6.0 * (w) * ((ux) * (cx) + (uy) * (cy) + (uz) * (cz)))
 
-// Moving-wall bounce-back for the directions in mask wm: the value pulled from
-// the wall cell x - c_q becomes f~_qbar(x) + 6 w_q (u_w . c_q) (deviations:
-// the weights cancel).  Only the z wall layers move (the layer z = 0 with
-// wall_u_lo, z = nz - 1 with wall_u_hi; edge cells belong to the z layers).
-template <typename T>
-__device__ __forceinline__ void wall_values(const DevDomain& d, const T* __restrict__ src, size_t NN,
-                                         unsigned int idx, int z, unsigned int wm,
-                                         typename Store<T>::C* g) {
-  using C = typename Store<T>::C;
-#pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    if (!((wm >> q) & 1u)) continue;
-    double uc = 0.0;
-    if (d.walls[2]) {
-      const int zs = z - CZ[q];
-      if (zs == 0)
-        uc = d.wall_u_lo[0] * CX[q] + d.wall_u_lo[1] * CY[q] + d.wall_u_lo[2] * CZ[q];
-      else if (zs == d.nz - 1)
-        uc = d.wall_u_hi[0] * CX[q] + d.wall_u_hi[1] * CY[q] + d.wall_u_hi[2] * CZ[q];
-    }
-    const double v = (double)Store<T>::load(src + (size_t)OPP[q] * NN + idx);
-    g[q] = (C)(v + 6.0 * WQ[q] * uc);
-  }
-}
+// The five directions whose source lies across one wall layer, per side.  The
+// x and y layers rest; a value from an edge cell shared with a z layer takes
+// that layer's velocity (the z rules run last).
+#define WALLS_XP(ux, uy, uz)                                              \
+  WALL_BB(4, 3, W1, 1, 0, 0, ux, uy, uz); WALL_BB(8, 9, W2, 1, 1, 0, ux, uy, uz); \
+  WALL_BB(10, 7, W2, 1, -1, 0, ux, uy, uz); WALL_BB(14, 17, W2, 1, 0, 1, ux, uy, uz); \
+  WALL_BB(18, 13, W2, 1, 0, -1, ux, uy, uz)
+#define WALLS_XM(ux, uy, uz)                                              \
+  WALL_BB(3, 4, W1, -1, 0, 0, ux, uy, uz); WALL_BB(7, 10, W2, -1, 1, 0, ux, uy, uz); \
+  WALL_BB(9, 8, W2, -1, -1, 0, ux, uy, uz); WALL_BB(13, 18, W2, -1, 0, 1, ux, uy, uz); \
+  WALL_BB(17, 14, W2, -1, 0, -1, ux, uy, uz)
+#define WALLS_YP(ux, uy, uz)                                              \
+  WALL_BB(1, 2, W1, 0, 1, 0, ux, uy, uz); WALL_BB(7, 10, W2, -1, 1, 0, ux, uy, uz); \
+  WALL_BB(8, 9, W2, 1, 1, 0, ux, uy, uz); WALL_BB(11, 16, W2, 0, 1, 1, ux, uy, uz); \
+  WALL_BB(15, 12, W2, 0, 1, -1, ux, uy, uz)
+#define WALLS_YM(ux, uy, uz)                                              \
+  WALL_BB(2, 1, W1, 0, -1, 0, ux, uy, uz); WALL_BB(9, 8, W2, -1, -1, 0, ux, uy, uz); \
+  WALL_BB(10, 7, W2, 1, -1, 0, ux, uy, uz); WALL_BB(12, 15, W2, 0, -1, 1, ux, uy, uz); \
+  WALL_BB(16, 11, W2, 0, -1, -1, ux, uy, uz)
+#define WALLS_ZP(ux, uy, uz)                                              \
+  WALL_BB(5, 6, W1, 0, 0, 1, ux, uy, uz); WALL_BB(11, 16, W2, 0, 1, 1, ux, uy, uz); \
+  WALL_BB(12, 15, W2, 0, -1, 1, ux, uy, uz); WALL_BB(13, 18, W2, -1, 0, 1, ux, uy, uz); \
+  WALL_BB(14, 17, W2, 1, 0, 1, ux, uy, uz)
+#define WALLS_ZM(ux, uy, uz)                                              \
+  WALL_BB(6, 5, W1, 0, 0, -1, ux, uy, uz); WALL_BB(15, 12, W2, 0, 1, -1, ux, uy, uz); \
+  WALL_BB(16, 11, W2, 0, -1, -1, ux, uy, uz); WALL_BB(17, 14, W2, -1, 0, -1, ux, uy, uz); \
+  WALL_BB(18, 13, W2, 1, 0, -1, ux, uy, uz)
 
 template <typename T>
 __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restrict__ src, T* __restrict__ dst,
@@ -134,11 +136,22 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
   g[18] = LD(18, X0, Y1, Z2);  // c = ( 1, 0,-1)
 #undef LD
 
-  unsigned int wm = 0u;
-  if (d.walls[2]) wm |= (z == 1 ? DIR_ZP : 0u) | (z == nz - 2 ? DIR_ZM : 0u);
-  if (d.walls[1]) wm |= (y == 1 ? DIR_YP : 0u) | (y == ny - 2 ? DIR_YM : 0u);
-  if (d.walls[0]) wm |= (x == 1 ? DIR_XP : 0u) | (x == nx - 2 ? DIR_XM : 0u);
-  if (wm) wall_values<T>(d, src, NN, idx, z, wm, g);
+  {
+    // cells next to a wall layer (block-uniform for z walls)
+    constexpr double W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
+    if (d.walls[0]) {
+      if (x == 1) { WALLS_XP(0.0, 0.0, 0.0); }
+      if (x == nx - 2) { WALLS_XM(0.0, 0.0, 0.0); }
+    }
+    if (d.walls[1]) {
+      if (y == 1) { WALLS_YP(0.0, 0.0, 0.0); }
+      if (y == ny - 2) { WALLS_YM(0.0, 0.0, 0.0); }
+    }
+    if (d.walls[2]) {
+      if (z == 1) { WALLS_ZP(d.wall_u_lo[0], d.wall_u_lo[1], d.wall_u_lo[2]); }
+      if (z == nz - 2) { WALLS_ZM(d.wall_u_hi[0], d.wall_u_hi[1], d.wall_u_hi[2]); }
+    }
+  }
 
   // moments (rho0 = 1: u = j; deviations carry no mass or momentum of w_q)
   const C sumd = ((g[7] + g[8]) + (g[9] + g[10])) + ((g[11] + g[12]) + (g[13] + g[14])) +
@@ -193,6 +206,13 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
 #pragma unroll
   for (int q = 0; q < Q; ++q) Store<T>::store(dst + (size_t)q * NN + idx, o[q]);
 }
+#undef WALL_BB
+#undef WALLS_XP
+#undef WALLS_XM
+#undef WALLS_YP
+#undef WALLS_YM
+#undef WALLS_ZP
+#undef WALLS_ZM
 
 // one domain: whole x-rows per block (see launch_sweep_t); the current buffer
 // is read from the domain's step state
