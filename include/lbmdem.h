@@ -155,8 +155,9 @@ int32_t lbmdem_update_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids,
 
 /* Motion mode of a sphere: LBMDEM_FREE, LBMDEM_FIXED (state never changes),
  * or LBMDEM_PRESCRIBED: velocity u_target (1 - exp(-c_acc t / t_st)) from rest
- * (Eq. artificial_acceleration), released to free motion once the gap to a
- * wall plane falls below release_gap. */
+ * (Eq. artificial_acceleration), released to free motion once the gap to the
+ * wall plane it approaches (ahead along u_target; Sec. 4.4.2) falls below
+ * release_gap.  Without a wall ahead it stays prescribed. */
 int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode,
                                const double* u_target, double c_acc, double t_st,
                                double release_gap);

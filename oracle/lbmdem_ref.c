@@ -420,6 +420,20 @@ static double min_wall_gap(const ref_domain* d, const sphere_t* s) {
   return g;
 }
 
+/* Sec. 4.4.2: the artificial acceleration is switched off once the sphere is
+ * closer than the release gap to the wall it approaches, i.e. the wall plane
+ * ahead of it along the prescribed velocity (only walled axes with a nonzero
+ * target component count); large if no wall lies ahead. */
+static double gap_ahead(const ref_domain* d, const sphere_t* s) {
+  double g = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    if (!d->cfg.walls[a] || s->utgt[a] == 0.0) continue;
+    double v = s->utgt[a] < 0.0 ? (s->x[a] - 1.0) - s->R : (((double)d->n[a] - 1.0) - s->x[a]) - s->R;
+    if (v < g) g = v;
+  }
+  return g;
+}
+
 static void remap(ref_domain* d, int reconstruct);
 
 int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
@@ -913,7 +927,7 @@ static void dem_substeps(ref_domain* d) {
   for (int sub = 0; sub < d->cfg.n_sub; ++sub) {
     for (int i = 0; i < P; ++i) {
       sphere_t* s = &d->sp[i];
-      if (s->mode == MODE_PRESCRIBED && min_wall_gap(d, s) < s->release_gap) {
+      if (s->mode == MODE_PRESCRIBED && gap_ahead(d, s) < s->release_gap) {
         s->mode = MODE_FREE;
         s->old_valid = 0;
       }

@@ -94,7 +94,8 @@ void ref_destroy(ref_domain* d);
 int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
                        const double* w, double R, double rho);
 /* mode 0 free, 1 prescribed ramp (u = u_target (1 - exp(-c_acc t / t_st)),
- * released when the gap to a wall drops below release_gap), 2 fixed */
+ * released when the gap to the wall plane ahead along u_target drops below
+ * release_gap), 2 fixed */
 int32_t ref_set_mode(ref_domain* d, int32_t id, int32_t mode,
                      const double* u_target, double c_acc, double t_st,
                      double release_gap);

@@ -58,18 +58,6 @@ __device__ inline void body_vel(const double* u, const double* w, const double* 
   U[2] = u[2] + wr[2];
 }
 
-__device__ inline double min_wall_gap(const DevDomain& d, const DevParticles& p, int i) {
-  double g = 1e300;
-  const int n[3] = {d.nx, d.ny, d.nz};
-  for (int a = 0; a < 3; ++a) {
-    if (!d.walls[a]) continue;
-    const double lo = (p.x[3 * i + a] - 1.0) - p.R[i];
-    const double hi = (((double)n[a] - 1.0) - p.x[3 * i + a]) - p.R[i];
-    g = fmin(g, fmin(lo, hi));
-  }
-  return g;
-}
-
 __device__ __forceinline__ void make_sphere_partner(const DevDomain& d, const DevParticles& p, int i, int j,
                                                     Partner& pt) {
   double dd[3];
@@ -339,9 +327,26 @@ __device__ __forceinline__ double list_range(const DevDomain& d) {
   return fmax(d.cut_n, fmax(d.cut_tt, d.cut_tr)) + d.skin;
 }
 
+// Gap of a prescribed sphere to the wall plane it approaches: the plane ahead
+// along its target velocity on every walled axis where that is nonzero
+// (Sec. 4.4.2 switches the acceleration off near the wall the sphere moves
+// to); large if there is none.
+__device__ inline double gap_ahead(const DevDomain& d, const DevParticles& p, int i) {
+  double g = 1e300;
+  const int n[3] = {d.nx, d.ny, d.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ut = p.presc[6 * i + a];
+    if (!d.walls[a] || ut == 0.0) continue;
+    const double v = ut < 0.0 ? (p.x[3 * i + a] - 1.0) - p.R[i] : (((double)n[a] - 1.0) - p.x[3 * i + a]) - p.R[i];
+    g = fmin(g, v);
+  }
+  return g;
+}
+
 // release of a prescribed sphere below its gap; start force of a newly free one
 __device__ __forceinline__ void release_and_start(const DevDomain& d, const DevParticles& p, int i, double dtp) {
-  if (p.mode[i] == MODE_PRESCRIBED && min_wall_gap(d, p, i) < p.presc[6 * i + 5]) {
+  if (p.mode[i] == MODE_PRESCRIBED && gap_ahead(d, p, i) < p.presc[6 * i + 5]) {
     p.mode[i] = MODE_FREE;
     p.old_valid[i] = 0;
   }

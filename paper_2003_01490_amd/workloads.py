@@ -15,6 +15,10 @@ Workloads:
                     density ratio U[2,8] and viscosity logU[0.005,0.05]
                     (rejecting u_s > 0.1), released from the ramp of
                     Eq. (artificial_acceleration) one diameter above the wall.
+  rebound_st27    - the St = 27 case of the sub-cycle study (Table
+                    sphereWallCollision_nsub_D20): 12 x 12 x 48 D with D 20,
+                    u_s 0.02, T_c and delta_min by the paper's relations, the
+                    start 3/2 D below the top wall perturbed by U[-1/2,1/2] in z.
   serve_requests  - a stream of independent sphere-wall requests with Poisson
                     arrivals (edges, diameter, Stokes number, density ratio
                     drawn per request), and serve_workload, the domain of one.
@@ -31,9 +35,10 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-# Table sphereWallCollision (Sec. 4.4.2), St = 100 row: fluid density, dynamic
-# viscosity, diameter, particle density, gravity (SI)
+# Table sphereWallCollision (Sec. 4.4.2), St = 100 and St = 27 rows: fluid
+# density, dynamic viscosity, diameter, particle density, gravity (SI)
 _ST100 = dict(rho_f=953.0, mu_f=0.02, D=0.004, rho_p=7800.0, g=9.81)
+_ST27 = dict(rho_f=965.0, mu_f=0.1, D=0.006, rho_p=7800.0, g=9.81)
 
 
 @dataclass
@@ -210,3 +215,31 @@ def serve_workload(req: dict) -> Workload:
     ramp = dict(u_target=(0.0, 0.0, -u_s), c_acc=10.0, t_st=t_st, release_gap=D)
     return Workload("serve", p, x[None], np.array([D / 2]), np.array([rho_r]), np.zeros((1, 3)),
                     np.zeros((1, 3)), 0, ramp=ramp, meta=dict(req))
+
+
+def rebound_st27(seed: int = 0, D: float = 20.0, u_s: float = 0.02, n_sub: int = 10) -> Workload:
+    """Sphere-wall collision at St = 27 (Sec. 4.4.2, parameter set SW9/SW10):
+    domain 12 x 12 x 48 diameters, density ratio 7800/965, the viscosity from
+    St = rho_r u_s D / (9 nu), gravity from the experiment's Froude number
+    g D / u_s^2, the sphere horizontally centred, 3/2 D below the top wall
+    plane, its height perturbed by U[-1/2, 1/2] (the paper perturbs the start
+    by one cell), ramped with c_acc = 10 and released one diameter above the
+    bottom wall."""
+    rng = np.random.default_rng(seed)
+    t = _ST27
+    rho_r = t["rho_p"] / t["rho_f"]
+    nu_phys = t["mu_f"] / t["rho_f"]
+    re = 30.0  # Table sphereWallCollision, St = 27 row
+    us_phys = re * nu_phys / t["D"]
+    St = rho_r * us_phys * t["D"] / (9.0 * nu_phys)
+    nu = rho_r * u_s * D / (9.0 * St)
+    fr = t["g"] * t["D"] / us_phys ** 2
+    g = fr * u_s ** 2 / D
+    n = int(round(12 * D)), int(round(12 * D)), int(round(48 * D))
+    x = np.array([n[0] / 2.0, n[1] / 2.0, (n[2] - 1.0) - 1.5 * D + rng.uniform(-0.5, 0.5)])
+    p = base_params(nx=n[0], ny=n[1], nz=n[2], nu=nu, n_sub=n_sub, gravity=(0.0, 0.0, -g), max_spheres=1)
+    t_st = rho_r * D * D / (18.0 * nu)
+    ramp = dict(u_target=(0.0, 0.0, -u_s), c_acc=10.0, t_st=t_st, release_gap=D)
+    return Workload("rebound_st27", p, x[None], np.array([D / 2]), np.array([rho_r]),
+                    np.zeros((1, 3)), np.zeros((1, 3)), 80000, ramp=ramp,
+                    meta=dict(seed=seed, St=St, u_s=u_s, rho_r=rho_r, nu=nu, g=g, froude=fr))

@@ -210,3 +210,32 @@ def test_tangential_spring_reset_at_separation_and_sticking():
     ucp_out = post["u"][0] - R * post["w"][1]
     assert ucp_out < 0.002 * 0.5  # sticking removes most of the slip
     assert te - ts > 0
+
+
+def test_prescribed_ramp_and_release_at_the_wall_ahead():
+    """Eq. (artificial_acceleration): u = u_s (1 - exp(-c_acc t / t_St)) with t
+    advanced per sub-step; the ramp is switched off once the gap to the wall
+    the sphere approaches (Sec. 4.4.2: the bottom wall for a settling sphere)
+    falls below the release gap.  A start closer than that to the wall behind
+    it must not release the sphere."""
+    R, n = 2.0, 24
+    cfg = O.make_config(nx=n, ny=n, nz=n, walls=(0, 0, 1), n_sub=10, max_spheres=1,
+                        gravity=(0.0, 0.0, -1e-4))
+    d = O.RefDomain(cfg)
+    z0 = (n - 1.0) - R - 1.0  # gap 1 to the top wall plane, behind the sphere
+    sid = d.add_sphere((n / 2, n / 2, z0), R, 3.0)
+    u_s, c_acc, t_st, gap_r = 0.5, 10.0, 40.0, 4.0
+    d.set_mode(sid, O.MODE_PRESCRIBED, (0.0, 0.0, -u_s), c_acc, t_st, gap_r)
+    released_at = None
+    for k in range(1, 60):
+        d.dem_step()
+        s = d.sphere(sid)
+        gap_bottom = s["x"][2] - 1.0 - R
+        if released_at is None and s["mode"] == O.MODE_FREE:
+            released_at = (k, gap_bottom)
+            break
+        assert s["mode"] == O.MODE_PRESCRIBED
+        assert gap_bottom >= gap_r - u_s / cfg.n_sub  # released within one sub-step of the gap
+        assert s["u"][2] == pytest.approx(-u_s * (1.0 - np.exp(-c_acc * k / t_st)), rel=1e-12)
+    assert released_at is not None, "never released above the bottom wall"
+    assert released_at[1] < gap_r
