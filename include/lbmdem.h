@@ -97,9 +97,10 @@ typedef struct lbmdem_config {
   int32_t max_spheres;      /* capacity, sizes the device region                 */
   double max_radius;        /* largest sphere radius that will be added          */
   int32_t dem_kernel;       /* DEM sub-cycle kernel: 0 automatic (one workgroup up
-                               to 256 spheres, else grid-wide), 1 one workgroup
-                               (all-pairs neighbour search), 2 grid-wide
-                               cooperative launch (binned neighbour search);
+                               to 256 spheres, else one thread per sphere), 1 one
+                               workgroup (all-pairs neighbour search), 2 one
+                               thread per sphere over a chain of launches
+                               (binned neighbour search);
                                results are identical                              */
   int32_t map_kernel;       /* boundary/commit pass: 0 automatic (one block per
                                sphere from 128 spheres when it fits), 1 several

@@ -73,7 +73,7 @@ int rowblocks(const lbmdem_config& c) {
   return std::min(full, per);
 }
 
-// uniform bins of the grid-wide neighbour search: edge at least the largest
+// uniform bins of the many-sphere neighbour search: edge at least the largest
 // centre distance of two listed neighbours (2 R_max + cut-off + skin), grown
 // if the count would exceed a few per sphere
 constexpr double NBR_SKIN = 1.0;
@@ -96,7 +96,7 @@ void bin_dims(const lbmdem_config& c, int* nb) {
 struct Layout {
   size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
-      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, barrier, ctl, partial, status;
+      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, ctl, partial, status;
   size_t total;
 };
 
@@ -147,7 +147,6 @@ Layout make_layout(const lbmdem_config& c) {
   int nb[3];
   bin_dims(c, nb);
   L.bins = take(4 * (size_t)nb[0] * nb[1] * nb[2] * (1 + BIN_CAP));
-  L.barrier = take(256);
   L.ctl = take(sizeof(DevCtl));
   L.partial = take(48 * P * (size_t)zblocks(c) * (size_t)rowblocks(c));
   L.status = take(256);
@@ -208,8 +207,6 @@ struct lbmdem_domain {
   std::vector<hipEvent_t> spare;
   double ms[3] = {0, 0, 0};
   int64_t cnt[3] = {0, 0, 0};
-  int grid_cap = 0;                   // co-resident blocks of the grid-wide DEM kernel
-  unsigned long long bar_base = 0;    // arrivals at the grid-wide barriers so far
   lbmdem_batch* batch = nullptr;      // batch the domain is admitted to
   // second stream of an overlapped step (created on first use) and the events
   // that fork it from and join it to the domain's stream
@@ -408,7 +405,6 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   p.w2 = (double*)(base + L.w2);
   bin_dims(*cfg, d.bins.n);
   d.bins.cell = (int*)(base + L.bins);
-  d.barrier = (unsigned long long*)(base + L.barrier);
   d.ctl = (DevCtl*)(base + L.ctl);
   d.P = 0;
   d.ZB = zblocks(*cfg);
@@ -431,7 +427,6 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.lub_mask = cfg->lub_mask;
   d.nu = cfg->nu;
   d.skin = NBR_SKIN;
-  dom->grid_cap = dem_grid_capacity();
   hipStream_t s = dom->stream;
   const size_t Pm = (size_t)std::max(cfg->max_spheres, 1);
 
@@ -628,14 +623,8 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, con
 
 // The DEM sub-cycles and the claims of step t need the forces formed by the
 // boundary pass of step t - 1 and the particle state, not the sweep of step
-// t, so with the one-workgroup DEM kernels they can run on a second stream
-// while the sweep runs.  (The grid-wide DEM kernel needs all its blocks
-// resident at once and stays on the domain's stream.)
-static bool overlap_step(const lbmdem_domain* dom) {
-  if (!dom->cfg.overlap || dom->d.P <= 0) return false;
-  const int k = dom->cfg.dem_kernel;
-  return !(k == 2 || (k == 0 && dom->d.P > DEM_GRID_MIN));
-}
+// t, so they can run on a second stream while the sweep runs.
+static bool overlap_step(const lbmdem_domain* dom) { return dom->cfg.overlap && dom->d.P > 0; }
 
 static int32_t ensure_side(lbmdem_domain* dom) {
   if (dom->side) return LBMDEM_OK;
@@ -668,7 +657,7 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
     }
     auto dem = [&] {
       timed(dom, 1, ds, [&] {
-        e = launch_dem(dom->d, dom->cfg.dem_kernel, dom->grid_cap, &dom->bar_base, ds);
+        e = launch_dem(dom->d, dom->cfg.dem_kernel, ds);
         launch_claim(dom->d, 1, ds);
       });
     };
@@ -706,10 +695,6 @@ int32_t lbmdem_sync(lbmdem_domain* dom) {
   if (st & (ST_HIST_FULL | ST_NBR_FULL)) {
     dom->failed = 1;
     return fail(dom, LBMDEM_ECAPACITY, "contact-history, neighbour-list or bin slots exhausted");
-  }
-  if (st & ST_BARRIER) {
-    dom->failed = 1;
-    return fail(dom, LBMDEM_EDEVICE, "a grid-wide barrier of the DEM kernel timed out");
   }
   return dom->failed ? LBMDEM_ESTATE : LBMDEM_OK;
 }
@@ -841,7 +826,7 @@ int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
 namespace {
 
 constexpr char CK_MAGIC[8] = {'L', 'B', 'M', 'D', 'E', 'M', 'C', 'K'};
-constexpr uint32_t CK_VERSION = 1;
+constexpr uint32_t CK_VERSION = 2;
 
 struct CkHeader {
   char magic[8];
@@ -849,8 +834,6 @@ struct CkHeader {
   uint32_t cfg_bytes;
   lbmdem_config cfg;
   int32_t cur;
-  int32_t pad0;
-  uint64_t bar_base;
   int32_t P;
   int32_t pad;
   uint64_t seg[3];  // bytes of: current PDF buffer, cell arrays, particle block
@@ -916,7 +899,6 @@ int32_t lbmdem_save(lbmdem_domain* dom, void* host_blob, size_t* bytes) {
   h.cfg_bytes = sizeof(lbmdem_config);
   h.cfg = dom->cfg;
   h.cur = c.cur;
-  h.bar_base = dom->bar_base;
   h.P = (int32_t)P;
   for (int k = 0; k < 3; ++k) h.seg[k] = len[k];
   char* out = (char*)host_blob;
@@ -961,7 +943,6 @@ int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes) 
     in += len[k];
   }
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
-  dom->bar_base = h.bar_base;
   dom->d.P = h.P;
   dom->failed = 0;
   return LBMDEM_OK;

@@ -17,11 +17,11 @@
 //
 // Two kernels.  Few spheres: one workgroup, sub-cycles separated by workgroup
 // barriers (with state, histories and lists in LDS up to DEM_LDS_MAX spheres).
-// Many spheres: one thread per sphere over a cooperative grid; neighbours are
-// found through uniform bins, and x, u, w alternate between two buffers every
-// sub-cycle (positions are advanced into the other buffer, then forces read
-// the new positions and the old velocities and write the new velocities into
-// the other buffer), so each sub-cycle needs only two grid-wide barriers.
+// Many spheres: one thread per sphere over a chain of launches; neighbours
+// are found through uniform bins, and x, u, w alternate between two buffers
+// every sub-cycle (positions are advanced into the other buffer, then forces
+// read the new positions and the old velocities and write the new velocities
+// into the other buffer), so each sub-cycle needs only two launches.
 #include "internal.hpp"
 
 #include <climits>
@@ -634,31 +634,6 @@ void launch_advance_batch(const BatchTables& b, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Grid-wide kernel for many spheres.
 
-// Barrier over all blocks of a cooperative launch: a monotonic arrival counter
-// (the host passes the count the launch starts from).  Every thread fences at
-// device scope on both sides, so the writes before the barrier are visible to
-// all blocks after it.  The wait is bounded: if it gives up (which a
-// cooperative launch should make impossible) the status word says so and the
-// kernel still runs to its end.
-__device__ __forceinline__ void grid_barrier(const DevDomain& d, unsigned long long& target, int* broken) {
-  target += gridDim.x;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(d.barrier, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (!*broken && __hip_atomic_load(d.barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > (1u << 22)) {
-        atomicOr(d.status, ST_BARRIER);
-        *broken = 1;
-      }
-    }
-  }
-  __syncthreads();
-  __threadfence();
-}
-
 __device__ __forceinline__ int bin_index(const DevDomain& d, const double* x, int* b) {
   const int n[3] = {d.nx, d.ny, d.nz};
   for (int a = 0; a < 3; ++a) {
@@ -748,106 +723,110 @@ __device__ __forceinline__ void binned_neighbours(const DevDomain& d, const DevP
   p.nbr_n[i] = cnt < NBR_MAX ? cnt : NBR_MAX;
 }
 
-// barriers of one grid-wide launch: two in the prologue, two per sub-cycle
-__host__ __device__ inline unsigned long long grid_barriers(const DevDomain& d) {
-  return 2ull + 2ull * (unsigned long long)d.n_sub;
+// Many spheres: one thread per sphere, the sub-cycles as a chain of ordinary
+// launches (a kernel boundary wherever every sphere must see the others'
+// state): the momentum-exchange sums and the bins, the neighbour lists, then
+// per sub-cycle the positions (into the other buffer) and the forces and
+// velocities (into the other buffer).  Ordinary launches can run beside the
+// sweep on a second stream, where a cooperative grid could not be sure of
+// having all its blocks resident.  Per sphere the arithmetic and its order are
+// those of the one-workgroup kernels (identical bits).
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_prologue(DevDomain d) {
+  if (dem_stopped(d)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (i >= d.P) return;
+  resolved_force(d, d.p, i, lane);
+  if (lane == 0) bin_insert(d, d.p, i);
 }
 
-__global__ __launch_bounds__(DEM_GRID_THREADS) void k_dem_grid(DevDomain d, unsigned long long base) {
-  if (dem_stopped(d)) {
-    // keep the arrival count what the host expects for this launch
-    if (threadIdx.x == 0) atomicAdd(d.barrier, grid_barriers(d));
-    return;
-  }
-  __shared__ int broken;
-  if (threadIdx.x == 0) broken = 0;
-  __syncthreads();
-  unsigned long long target = base;
-  const int P = d.P;
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_neighbours(DevDomain d) {
+  if (dem_stopped(d)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.P) binned_neighbours(d, d.p, i);
+}
+
+// state of sub-cycle `sub` (even: the first buffers), and the other buffer
+__device__ __forceinline__ void subcycle_buffers(const DevParticles& p, int sub, DevParticles& a, double** x1,
+                                                 double** u1, double** w1) {
+  const bool odd = sub & 1;
+  a = p;
+  a.x = odd ? p.x2 : p.x;
+  a.u = odd ? p.u2 : p.u;
+  a.w = odd ? p.w2 : p.w;
+  *x1 = odd ? p.x : p.x2;
+  *u1 = odd ? p.u : p.u2;
+  *w1 = odd ? p.w : p.w2;
+}
+
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_position(DevDomain d, int sub) {
+  if (dem_stopped(d)) return;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gstride = gridDim.x * blockDim.x;
-  const DevParticles p = d.p;
-  {
-    const int lane = threadIdx.x & 63;
-    for (int i = gtid >> 6; i < P; i += gstride >> 6) {
-      resolved_force(d, p, i, lane);
-      if (lane == 0) bin_insert(d, p, i);
-    }
+  if (sub == 0) {  // the lists are built: clear the bins for the next step
+    const int nbins = d.bins.n[0] * d.bins.n[1] * d.bins.n[2];
+    for (int k = gtid; k < nbins; k += gridDim.x * blockDim.x) d.bins.cell[(size_t)k * (1 + BIN_CAP)] = 0;
   }
-  grid_barrier(d, target, &broken);
-  for (int i = gtid; i < P; i += gstride) binned_neighbours(d, p, i);
-  grid_barrier(d, target, &broken);
-  const int nbins = d.bins.n[0] * d.bins.n[1] * d.bins.n[2];
+  if (gtid >= d.P) return;
+  DevParticles a;
+  double *x1, *u1, *w1;
+  subcycle_buffers(d.p, sub, a, &x1, &u1, &w1);
   const double dtp = 1.0 / (double)d.n_sub;
-  for (int sub = 0; sub < d.n_sub; ++sub) {
-    const bool odd = sub & 1;  // state in the second buffers
-    double* const x0 = odd ? p.x2 : p.x;
-    double* const u0 = odd ? p.u2 : p.u;
-    double* const w0 = odd ? p.w2 : p.w;
-    double* const x1 = odd ? p.x : p.x2;
-    double* const u1 = odd ? p.u : p.u2;
-    double* const w1 = odd ? p.w : p.w2;
-    if (sub == 0)  // the lists are built: clear the bins for the next step
-      for (int k = gtid; k < nbins; k += gstride) d.bins.cell[(size_t)k * (1 + BIN_CAP)] = 0;
-    DevParticles a = p;  // state at the start of the sub-cycle
-    a.x = x0;
-    a.u = u0;
-    a.w = w0;
-    for (int i = gtid; i < P; i += gstride) {
-      release_and_start(d, a, i, dtp);
-      advance_position(d, a, i, dtp, x1 + 3 * i);
-    }
-    grid_barrier(d, target, &broken);
-    DevParticles b = a;  // new positions, old velocities
-    b.x = x1;
-    for (int i = gtid; i < P; i += gstride) {
-      eval_forces(d, b, i, true, true, dtp, p.Fnew + 6 * i, p.Fnew + 6 * i + 3);
-      advance_velocity(d, b, i, dtp, u1 + 3 * i, w1 + 3 * i);
-    }
-    grid_barrier(d, target, &broken);
-  }
-  for (int i = gtid; i < P; i += gstride) {
-    if (d.n_sub & 1)
-      for (int a = 0; a < 3; ++a) {
-        p.x[3 * i + a] = p.x2[3 * i + a];
-        p.u[3 * i + a] = p.u2[3 * i + a];
-        p.w[3 * i + a] = p.w2[3 * i + a];
-      }
-    health_check(d, p, i);
-  }
+  release_and_start(d, a, gtid, dtp);
+  advance_position(d, a, gtid, dtp, x1 + 3 * gtid);
 }
 
-int dem_grid_capacity() {
-  int dev = 0, ncu = 0, nb = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_dem_grid),
-                                                   DEM_GRID_THREADS, 0) != hipSuccess)
-    return 0;
-  return nb * ncu;
+// forces at the new positions with the old velocities, new velocities into
+// the other buffer; after the last sub-cycle the state is copied back if it
+// ended in the second buffers (odd n_sub, a kernel of its own) and checked
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_velocity(DevDomain d, int sub) {
+  if (dem_stopped(d)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.P) return;
+  DevParticles a;
+  double *x1, *u1, *w1;
+  subcycle_buffers(d.p, sub, a, &x1, &u1, &w1);
+  DevParticles b = a;
+  b.x = x1;
+  const double dtp = 1.0 / (double)d.n_sub;
+  eval_forces(d, b, i, true, true, dtp, d.p.Fnew + 6 * i, d.p.Fnew + 6 * i + 3);
+  advance_velocity(d, b, i, dtp, u1 + 3 * i, w1 + 3 * i);
+  if (sub == d.n_sub - 1 && !(d.n_sub & 1)) health_check(d, d.p, i);
 }
 
-hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
-                      hipStream_t s) {
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_epilogue(DevDomain d) {
+  if (dem_stopped(d)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.P) return;
+  const DevParticles& p = d.p;
+  for (int a = 0; a < 3; ++a) {
+    p.x[3 * i + a] = p.x2[3 * i + a];
+    p.u[3 * i + a] = p.u2[3 * i + a];
+    p.w[3 * i + a] = p.w2[3 * i + a];
+  }
+  health_check(d, p, i);
+}
+
+bool dem_many(const DevDomain& d, int kernel) { return kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN); }
+
+hipError_t launch_dem(const DevDomain& d, int kernel, hipStream_t s) {
   if (d.P <= 0) return hipSuccess;
-  const bool grid = kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN);
-  if (!grid) {
+  if (!dem_many(d, kernel)) {
     if (d.P <= DEM_LDS_MAX)
       hipLaunchKernelGGL(k_dem_lds, dim3(1), dim3(256), 0, s, d);
     else
       hipLaunchKernelGGL(k_dem, dim3(1), dim3(256), 0, s, d);
     return hipGetLastError();
   }
-  if (grid_cap <= 0) return hipErrorInvalidConfiguration;
-  const int want = (d.P + DEM_GRID_THREADS - 1) / DEM_GRID_THREADS;
-  const int blocks = want < grid_cap ? want : grid_cap;
-  DevDomain dd = d;
-  unsigned long long base = *barrier_base;
-  void* args[] = {&dd, &base};
-  hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_dem_grid), dim3(blocks),
-                                            dim3(DEM_GRID_THREADS), args, 0, s);
-  if (e == hipSuccess) *barrier_base += (unsigned long long)blocks * grid_barriers(d);
-  return e;
+  const unsigned T = DEM_GRID_THREADS;
+  const unsigned blocks = (unsigned)((d.P + T - 1) / T);
+  hipLaunchKernelGGL(k_demg_prologue, dim3((unsigned)(((long long)d.P * 64 + T - 1) / T)), dim3(T), 0, s, d);
+  hipLaunchKernelGGL(k_demg_neighbours, dim3(blocks), dim3(T), 0, s, d);
+  for (int sub = 0; sub < d.n_sub; ++sub) {
+    hipLaunchKernelGGL(k_demg_position, dim3(blocks), dim3(T), 0, s, d, sub);
+    hipLaunchKernelGGL(k_demg_velocity, dim3(blocks), dim3(T), 0, s, d, sub);
+  }
+  if (d.n_sub & 1) hipLaunchKernelGGL(k_demg_epilogue, dim3(blocks), dim3(T), 0, s, d);
+  return hipGetLastError();
 }
 
 }  // namespace lbmdem

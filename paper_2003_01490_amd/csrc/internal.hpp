@@ -39,7 +39,6 @@ constexpr int MODE_FIXED = 2;
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_HIST_FULL = 2;
 constexpr int ST_NBR_FULL = 4;
-constexpr int ST_BARRIER = 8;    // a grid-wide barrier gave up waiting
 
 constexpr int BIN_CAP = 15;      // sphere ids per neighbour-search bin (+1 count)
 
@@ -103,12 +102,12 @@ struct DevParticles {
   double* hist_d; // [P][HIST_SLOTS][3] tangential spring
   int* nbr;       // [P][NBR_MAX] candidate partners (ascending)
   int* nbr_n;     // [P]
-  double* x2;     // [P][3] second buffers of x, u, w: the grid-wide DEM
+  double* x2;     // [P][3] second buffers of x, u, w: the many-sphere DEM
   double* u2;     //        kernel alternates between the two every sub-cycle
   double* w2;
 };
 
-// uniform bins of the grid-wide neighbour search: edge >= the largest centre
+// uniform bins of the many-sphere neighbour search: edge >= the largest centre
 // distance at which two spheres can be neighbours
 struct DevBins {
   int n[3];       // bins per axis
@@ -149,7 +148,6 @@ struct DevDomain {
   double nu;
   double skin;     // neighbour-list skin
   DevBins bins;
-  unsigned long long* barrier;  // arrival counter of the grid-wide barriers
 };
 
 __host__ __device__ inline long long cidx(const DevDomain& d, int i, int j, int k) {
@@ -212,16 +210,13 @@ void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_
 // buffers, move the stamp and evaluate the stop rule
 void launch_advance(const DevDomain& d, hipStream_t s);
 void launch_advance_batch(const BatchTables& b, hipStream_t s);
-// DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 grid-wide
-// (cooperative).  *barrier_base is the arrival count the grid barriers start
-// from; it is advanced by the arrivals of the launch.
-// grid_cap: co-resident blocks of the grid-wide kernel (dem_grid_capacity()).
-hipError_t launch_dem(const DevDomain& d, int kernel, int grid_cap, unsigned long long* barrier_base,
-                      hipStream_t s);
-// co-resident blocks of the grid-wide DEM kernel on the current device
-int dem_grid_capacity();
+// DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 one thread per
+// sphere over a chain of launches (binned neighbour search).
+hipError_t launch_dem(const DevDomain& d, int kernel, hipStream_t s);
+// whether launch_dem takes the many-sphere chain
+bool dem_many(const DevDomain& d, int kernel);
 constexpr int DEM_GRID_THREADS = 128;
-// automatic DEM kernel choice: above this many spheres the grid-wide kernel
+// automatic DEM kernel choice: above this many spheres the many-sphere chain
 constexpr int DEM_GRID_MIN = 256;
 void launch_fields(const DevDomain& d, int field, double* dst, hipStream_t s);
 void launch_set_pdf(const DevDomain& d, int q, const double* src, hipStream_t s);

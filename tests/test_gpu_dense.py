@@ -1,5 +1,5 @@
 """Many spheres: the GPU path against the FP64 oracle, the two DEM kernels (one
-workgroup with an all-pairs neighbour search; grid-wide with binned search)
+workgroup with an all-pairs neighbour search; one thread per sphere with binned search)
 against each other, and both boundary passes (several blocks per sphere; one
 block per sphere with its cells staged in LDS) against the oracle.
 
@@ -162,7 +162,7 @@ def test_dense_full_size_properties():
 
     wl = W.dense(0, n=384, count=10000, steps=1000)
     P = len(wl.R)
-    _case(f"dense 384^3, {P} spheres, FP32 storage, automatic DEM kernel (grid-wide)")
+    _case(f"dense 384^3, {P} spheres, FP32 storage, automatic DEM kernel (one thread per sphere)")
     g = gpu_domain(wl, storage=L.STORE_F32)
     g.step(1)
     g.sync()

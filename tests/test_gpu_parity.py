@@ -175,7 +175,7 @@ def test_settling_sphere_32_fp64(seed):
 
 def test_contact_variant_fp64():
     """Contact and lubrication with the wall; the workgroup DEM kernel (LDS
-    variant) and the grid-wide one side by side."""
+    variant) and the one-thread-per-sphere one side by side."""
     wl = W.contact_32(0)
     _case(f"contact_32 FP64, {wl.steps} steps, DEM kernels 1 and 2")
     o = oracle_domain(wl)
