@@ -674,10 +674,7 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
       dom->failed = 1;
       return fail(dom, LBMDEM_EDEVICE, std::string("DEM launch failed: ") + hipGetErrorString(e));
     }
-    timed(dom, 2, s, [&] {
-      launch_update(dom->d, true, 1, s);
-      launch_advance(dom->d, s);
-    });
+    timed(dom, 2, s, [&] { launch_update_and_advance(dom->d, s); });
   }
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;

@@ -462,49 +462,6 @@ __device__ __forceinline__ void dem_body(const DevDomain& d, const DevParticles&
 // control kernel then freezes it).
 __device__ __forceinline__ bool dem_stopped(const DevDomain& d) { return !step_live(d.ctl); }
 
-// At the end of the step, by one thread, after the sweep, the DEM and the
-// mapping update: count the step, flip the current PDF buffer (the sweep has
-// written the other one, the mapping update completed it), move the mapping
-// stamp to the claims of the new positions, and evaluate the stop rule.  The
-// rebound rule follows sphere 0: approach, wall or sphere contact (collision
-// force of the last sub-cycle non-zero), contact over, rising (u_z > 0), apex
-// (u_z <= 0 again).
-__device__ __forceinline__ void advance_step(const DevDomain& d, const DevParticles& p) {
-  DevCtl* c = d.ctl;
-  c->steps += 1;
-  c->cur ^= 1;
-  c->stamp += 1;
-  bool stop = c->max_steps > 0 && c->steps >= c->max_steps;
-  if (c->stop_rule == STOP_REBOUND && d.P > 0) {
-    const bool contact = p.diag[12] != 0.0 || p.diag[13] != 0.0 || p.diag[14] != 0.0;
-    const double uz = p.u[2];
-    int ph = c->rb_phase;
-    if (ph == 0 && contact)
-      ph = 1;
-    else if (ph == 1 && !contact)
-      ph = 2;
-    else if (ph == 2 && uz > 0.0)
-      ph = 3;
-    else if (ph == 3 && uz <= 0.0)
-      stop = true;
-    c->rb_phase = ph;
-  }
-  if (stop) c->stop_req = 1;
-}
-
-// Step control, one thread: a domain whose stop rule was met at the end of
-// the last step (and which therefore skipped this step) freezes; otherwise
-// the step is completed.
-__device__ __forceinline__ void step_control(const DevDomain& d) {
-  DevCtl* c = d.ctl;
-  if (c->frozen) return;
-  if (c->stop_req) {
-    c->frozen = 1;
-    return;
-  }
-  advance_step(d, d.p);
-}
-
 __global__ void k_advance(DevDomain d) { step_control(d); }
 
 __global__ void k_advance_batch(const DevDomain* __restrict__ tab, int ndom) {

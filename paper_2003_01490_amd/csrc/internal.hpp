@@ -69,6 +69,7 @@ struct DevCtl {
   int64_t max_steps;  // stop after this many steps (<= 0: never)
   int32_t stop_rule;  // 0 none, 1 rebound of sphere 0 (first apex after its first wall contact)
   int32_t rb_phase;   // rebound tracking: 0 approach, 1 contact, 2 after contact, 3 rising
+  uint32_t done_blocks;  // blocks of the step's last kernel that have finished (see k_commit)
 };
 
 // A step's kernels do nothing for a domain that is frozen or whose stop rule
@@ -196,6 +197,49 @@ __device__ __forceinline__ int batch_domain(const int* start, int ndom, int b) {
   return lo;
 }
 
+// At the end of the step, by one thread, after the sweep, the DEM and the
+// mapping update: count the step, flip the current PDF buffer (the sweep has
+// written the other one, the mapping update completed it), move the mapping
+// stamp to the claims of the new positions, and evaluate the stop rule.  The
+// rebound rule follows sphere 0: approach, wall or sphere contact (collision
+// force of the last sub-cycle non-zero), contact over, rising (u_z > 0), apex
+// (u_z <= 0 again).
+__device__ inline void advance_step(const DevDomain& d, const DevParticles& p) {
+  DevCtl* c = d.ctl;
+  c->steps += 1;
+  c->cur ^= 1;
+  c->stamp += 1;
+  bool stop = c->max_steps > 0 && c->steps >= c->max_steps;
+  if (c->stop_rule == STOP_REBOUND && d.P > 0) {
+    const bool contact = p.diag[12] != 0.0 || p.diag[13] != 0.0 || p.diag[14] != 0.0;
+    const double uz = p.u[2];
+    int ph = c->rb_phase;
+    if (ph == 0 && contact)
+      ph = 1;
+    else if (ph == 1 && !contact)
+      ph = 2;
+    else if (ph == 2 && uz > 0.0)
+      ph = 3;
+    else if (ph == 3 && uz <= 0.0)
+      stop = true;
+    c->rb_phase = ph;
+  }
+  if (stop) c->stop_req = 1;
+}
+
+// Step control, one thread: a domain whose stop rule was met at the end of
+// the last step (and which therefore skipped this step) freezes; otherwise
+// the step is completed.
+__device__ inline void step_control(const DevDomain& d) {
+  DevCtl* c = d.ctl;
+  if (c->frozen) return;
+  if (c->stop_req) {
+    c->frozen = 1;
+    return;
+  }
+  advance_step(d, d.p);
+}
+
 // host-side launchers (implemented in the .hip files)
 void launch_sweep(const DevDomain& d, hipStream_t s);
 // mapping update outside the step: claim + (reconstruction) + commit/boundary
@@ -206,6 +250,9 @@ void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s);
 // control), 0 for an update outside the step
 void launch_claim(const DevDomain& d, int in_step, hipStream_t s);
 void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s);
+// the same inside a step, ending with the step control (folded into the last
+// block of the boundary pass, or its own kernel when there is none)
+void launch_update_and_advance(const DevDomain& d, hipStream_t s);
 // step control (last kernel of a step): freeze, or count the step, flip the
 // buffers, move the stamp and evaluate the stop rule
 void launch_advance(const DevDomain& d, hipStream_t s);

@@ -511,6 +511,102 @@ __device__ inline void link_batch(const LinkCtx<T>& c, double* acc) {
 }
 
 template <typename T>
+__device__ __forceinline__ double raw_to_d(T v);
+template <>
+__device__ __forceinline__ double raw_to_d<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double raw_to_d<float>(float v) { return (double)v; }
+template <>
+__device__ __forceinline__ double raw_to_d<__half>(__half v) { return (double)__half2float(v); }
+
+// All 18 directions of a solid cell y of sphere i at once, for the few-sphere
+// boundary pass, which is bound by memory latency rather than traffic: the
+// PDF loads of every direction are issued unconditionally (a neighbour's own
+// slots stand in where a direction needs no value) before any is used, and
+// the boundary values are stored after all of them are formed, so the cell
+// costs one memory round trip instead of one per batch.  Arithmetic as in
+// link_batch.
+template <typename T>
+__device__ inline void link_all(const LinkCtx<T>& c, double* acc) {
+  const DevDomain& d = c.d;
+  int code[Q];
+  bool cli[Q];
+  T vq[Q], vqb[Q], vm[Q];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    const int cq0 = CX[q], cq1 = CY[q], cq2 = CZ[q];
+    const int xi = wrapi(c.ii - cq0, d.nx), xj = wrapi(c.jj - cq1, d.ny), xk = wrapi(c.kk - cq2, d.nz);
+    const long long xg = cidx(d, xi, xj, xk);
+    if (c.staged) {
+      code[q] = c.st[c.cidx0 - cq0 - c.HX * (cq1 + c.HY * cq2)];
+    } else {
+      int zo = -1;
+      const int zs = new_state(d, xg, c.stamp, &zo);
+      code[q] = zs == S_WALL ? L_WALL : (zs == S_SOLID ? (zo == c.i ? L_OWN : L_OTHER) : (zs == S_SHELL ? L_SHELL : L_FLUID));
+    }
+    long long xm = xg;
+    cli[q] = false;
+    if (code[q] <= L_SHELL && d.boundary == 0) {
+      const long long xmg = cidx(d, wrapi(xi - cq0, d.nx), wrapi(xj - cq1, d.ny), wrapi(xk - cq2, d.nz));
+      if (c.staged) {
+        cli[q] = c.st[c.cidx0 - 2 * cq0 - c.HX * (2 * cq1 + c.HY * 2 * cq2)] <= L_SHELL;
+      } else {
+        int mo;
+        cli[q] = is_fluid_state(new_state(d, xmg, c.stamp, &mo));
+      }
+      if (cli[q]) xm = xmg;
+    }
+    vq[q] = c.buf[(size_t)q * c.N + xg];
+    vqb[q] = c.buf[(size_t)OPP[q] * c.N + xg];
+    vm[q] = c.buf[(size_t)q * c.N + xm];
+  }
+  double val[Q];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    val[q] = 0.0;
+    if (code[q] == L_OWN) continue;
+    const int cq[3] = {CX[q], CY[q], CZ[q]};
+    double Fq[3], arm[3];
+    if (code[q] <= L_SHELL) {
+      const double gq = raw_to_d<T>(vq[q]), gqb = raw_to_d<T>(vqb[q]), gm = raw_to_d<T>(vm[q]);
+      const int xi = wrapi(c.ii - cq[0], d.nx), xj = wrapi(c.jj - cq[1], d.ny), xk = wrapi(c.kk - cq[2], d.nz);
+      double r[3];
+      r[0] = min_image(((double)xi + 0.5) - c.xp[0], d.nx, d.walls[0]);
+      r[1] = min_image(((double)xj + 0.5) - c.xp[1], d.ny, d.walls[1]);
+      r[2] = min_image(((double)xk + 0.5) - c.xp[2], d.nz, d.walls[2]);
+      const double dl = link_delta(r, cq, c.R);
+      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * cq[a];
+      double ub[3];
+      ub[0] = c.up[0] + (c.wp[1] * arm[2] - c.wp[2] * arm[1]);
+      ub[1] = c.up[1] + (c.wp[2] * arm[0] - c.wp[0] * arm[2]);
+      ub[2] = c.up[2] + (c.wp[0] * arm[1] - c.wp[1] * arm[0]);
+      const double dd = cli[q] ? dl : 0.5;
+      double v = gq;
+      if (cli[q]) v += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (gm - gqb);
+      v -= 4.0 / (1.0 + 2.0 * dd) * WQ[q] * 3.0 * (ub[0] * cq[0] + ub[1] * cq[1] + ub[2] * cq[2]);
+      val[q] = v;
+      const double fq = gq + WQ[q], fb = v + WQ[q];
+      for (int a = 0; a < 3; ++a) Fq[a] = (cq[a] - ub[a]) * fq - (-cq[a] - ub[a]) * fb;
+    } else {
+      // wall or another sphere's solid: missing link, F_q = 2 w_q c_q
+      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * WQ[q] * cq[a];
+      arm[0] = min_image(((double)c.ii + 0.5) - c.xp[0], d.nx, d.walls[0]) - 0.5 * cq[0];
+      arm[1] = min_image(((double)c.jj + 0.5) - c.xp[1], d.ny, d.walls[1]) - 0.5 * cq[1];
+      arm[2] = min_image(((double)c.kk + 0.5) - c.xp[2], d.nz, d.walls[2]) - 0.5 * cq[2];
+    }
+    acc[0] += Fq[0];
+    acc[1] += Fq[1];
+    acc[2] += Fq[2];
+    acc[3] += arm[1] * Fq[2] - arm[2] * Fq[1];
+    acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
+    acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
+  }
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+    if (code[q] <= L_SHELL) stv<T>(c.buf + (size_t)OPP[q] * c.N + c.yc, val[q]);
+}
+
+template <typename T>
 __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cur, uint32_t stamp) {
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
@@ -550,15 +646,16 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
       const int nrow = min(COMMIT_ROWS, EY - ry0);
       if (staged && cuts) {
         __syncthreads();
-        // four entries per thread and pass, all loads issued before any use
+        // eight entries per thread and pass (one pass for boxes up to ~40
+        // cells wide), all loads issued before any use
         const int NS = HX * HY * 5;
-        for (int t0 = threadIdx.x; t0 < NS; t0 += 4 * blockDim.x) {
-          bool in[4];
-          uint8_t fl[4];
-          unsigned long long kc[4];
-          uint32_t ss[4];
+        for (int t0 = threadIdx.x; t0 < NS; t0 += 8 * blockDim.x) {
+          bool in[8];
+          uint8_t fl[8];
+          unsigned long long kc[8];
+          uint32_t ss[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 8; ++u) {
             const int t = t0 + u * blockDim.x;
             const int hx = t % HX, r = t / HX, hy = r % HY, hz = r / HY;
             const int gx = bx.lo[0] - 2 + hx, gy = bx.lo[1] + ry0 - 2 + hy, gz = kz - 2 + hz;
@@ -572,7 +669,7 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
             }
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 8; ++u) {
             const int t = t0 + u * blockDim.x;
             if (t >= NS) continue;
             uint8_t code = L_WALL;
@@ -598,17 +695,28 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
         const double dn2 = cell_d2(d, ii, jj, kk, xp);
         if (!(dn2 <= rs2) && !(cell_d2(d, ii, jj, kk, xo) <= rs2)) continue;
         const long long yc = cidx(d, ii, jj, kk);
-        int own = -1;
-        const int ns = new_state(d, yc, stamp, &own);
+        const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
+        // the cell's state: staged when its plane cuts the solid ball (then
+        // only another sphere's solid needs the claim for its owner)
+        const bool stg = staged && cuts;
+        const int sc = stg ? (int)st[cidx0] : -1;
+        int own = -1, ns;
+        if (sc == L_OWN) {
+          ns = S_SOLID;
+          own = i;
+        } else if (sc == L_SHELL || sc == L_FLUID) {
+          ns = sc == L_SHELL ? S_SHELL : S_FLUID;
+        } else if (sc == L_WALL) {
+          ns = S_WALL;
+        } else {
+          ns = new_state(d, yc, stamp, &own);
+        }
         if (ns == S_WALL) continue;
         d.flags[yc] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
         if (ns == S_SOLID) d.owner[yc] = own;
         if (!(ns == S_SOLID && own == i)) continue;
-        const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
-        const LinkCtx<T> lc{d, buf, N, st, staged, cidx0, HX, HY, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
-        link_batch<T, 1>(lc, acc);
-        link_batch<T, 7>(lc, acc);
-        link_batch<T, 13>(lc, acc);
+        const LinkCtx<T> lc{d, buf, N, st, stg, cidx0, HX, HY, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
+        link_all<T>(lc, acc);
       }
     }
   }
@@ -629,10 +737,30 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
   }
 }
 
+constexpr int FOLD_ADVANCE_MAX_BLOCKS = 512;
+
+// With `advance`, the last block of the launch to finish runs the step
+// control (saving a launch at the end of the step): every block has read the
+// step state by the time it counts itself done, so none can see it change.
+__device__ __forceinline__ void last_block_advance(const DevDomain& d) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&d.ctl->done_blocks, 1u) == gridDim.x - 1u;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    d.ctl->done_blocks = 0u;
+    step_control(d);
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step) {
-  if (!map_live(d.ctl, in_step)) return;
-  commit_block<T>(d, blockIdx.x, map_buffer(d.ctl, in_step), map_stamp(d.ctl));
+__global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step, int advance) {
+  if (map_live(d.ctl, in_step)) commit_block<T>(d, blockIdx.x, map_buffer(d.ctl, in_step), map_stamp(d.ctl));
+  if (advance) last_block_advance(d);
 }
 
 // Many spheres: one block per sphere.  The states of all cells within R + 3 of
@@ -645,13 +773,11 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step) {
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int in_step) {
-  if (!map_live(d.ctl, in_step)) return;
+__device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step) {
   const int cur = map_buffer(d.ctl, in_step);
   const uint32_t stamp = map_stamp(d.ctl);
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
-  if ((int)blockIdx.x >= d.P) return;
   extern __shared__ uint8_t smem[];
   const int he = d.stage_edge, H = he / 2;
   const int NS = he * he * he;
@@ -822,6 +948,12 @@ __global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int in_step) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_commit_ball(DevDomain d, int in_step, int advance) {
+  if (map_live(d.ctl, in_step) && (int)blockIdx.x < d.P) commit_ball<T>(d, in_step);
+  if (advance) last_block_advance(d);
+}
+
 
 void launch_claim(const DevDomain& d, int in_step, hipStream_t s) {
   const int nsb = d.P * d.ZB;
@@ -829,27 +961,42 @@ void launch_claim(const DevDomain& d, int in_step, hipStream_t s) {
 }
 
 template <typename T>
-static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s) {
+static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb <= 0) return;
+  if (nsb <= 0) {
+    if (advance) launch_advance(d, s);
+    return;
+  }
   if (reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, in_step);
+  // The step control rides on the last block only where the launch has few
+  // blocks: the count of finished blocks is one device-wide atomic per block,
+  // which costs more than the saved launch once there are thousands.
+  const int blocks = d.map_ball ? d.P : nsb * d.RB;
+  const int fold = advance && blocks <= FOLD_ADVANCE_MAX_BLOCKS;
   if (d.map_ball) {
     const size_t lds = (((size_t)d.stage_edge * d.stage_edge * d.stage_edge + 15) & ~(size_t)15) +
                        2 * (size_t)d.list_cap;
-    hipLaunchKernelGGL(k_commit_ball<T>, dim3(d.P), dim3(256), lds, s, d, in_step);
-    return;
+    hipLaunchKernelGGL(k_commit_ball<T>, dim3(blocks), dim3(256), lds, s, d, in_step, fold);
+  } else {
+    hipLaunchKernelGGL(k_commit<T>, dim3(blocks), dim3(256), 0, s, d, in_step, fold);
   }
-  hipLaunchKernelGGL(k_commit<T>, dim3(nsb * d.RB), dim3(256), 0, s, d, in_step);
+  if (advance && !fold) launch_advance(d, s);
+}
+
+static void launch_update_any(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
+  if (d.storage == 0)
+    launch_update_t<double>(d, reconstruct, in_step, advance, s);
+  else if (d.storage == 1)
+    launch_update_t<float>(d, reconstruct, in_step, advance, s);
+  else
+    launch_update_t<__half>(d, reconstruct, in_step, advance, s);
 }
 
 void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s) {
-  if (d.storage == 0)
-    launch_update_t<double>(d, reconstruct, in_step, s);
-  else if (d.storage == 1)
-    launch_update_t<float>(d, reconstruct, in_step, s);
-  else
-    launch_update_t<__half>(d, reconstruct, in_step, s);
+  launch_update_any(d, reconstruct, in_step, 0, s);
 }
+
+void launch_update_and_advance(const DevDomain& d, hipStream_t s) { launch_update_any(d, true, 1, 1, s); }
 
 void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
   launch_claim(d, 0, s);
