@@ -1035,6 +1035,10 @@ struct lbmdem_batch {
   std::vector<int> built_P;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // side stream of the DEM and the claims beside the sweep, and the events
+  // that fork and join it (also inside a captured graph)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
 };
 
@@ -1109,11 +1113,22 @@ static int32_t build_tables(lbmdem_batch* b) {
   return LBMDEM_OK;
 }
 
-static void launch_batch_step(lbmdem_batch* b) {
+// One step of every domain: the sweep and, beside it on the side stream, the
+// DEM sub-cycles and the claims (they need the previous step's forces only);
+// then reconstruction, the boundary pass and the step control.
+static hipError_t launch_batch_step(lbmdem_batch* b) {
+  hipError_t e = hipEventRecord(b->ev_fork, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  launch_dem_batch(b->t, b->side);
+  launch_claim_batch(b->t, b->side);
   launch_sweep_batch(b->t, b->stream);
-  launch_dem_batch(b->t, b->stream);
-  launch_mapping_batch(b->t, b->stream);
+  e = hipEventRecord(b->ev_join, b->side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join, 0);
+  if (e != hipSuccess) return e;
+  launch_update_batch(b->t, b->stream);
   launch_advance_batch(b->t, b->stream);
+  return hipGetLastError();
 }
 
 extern "C" {
@@ -1124,6 +1139,14 @@ int32_t lbmdem_batch_create(void* hip_stream, size_t pool_bytes, lbmdem_batch** 
   if (!b) return LBMDEM_ENOMEM;
   b->stream = (hipStream_t)hip_stream;
   b->pool = pool_bytes;
+  if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    delete b;
+    return LBMDEM_EDEVICE;
+  }
   *out = b;
   return LBMDEM_OK;
 }
@@ -1134,6 +1157,10 @@ int32_t lbmdem_batch_destroy(lbmdem_batch* b) {
   drop_graph(b);
   for (auto* d : b->doms) d->batch = nullptr;
   if (b->dmem) (void)hipFree(b->dmem);
+  (void)hipStreamSynchronize(b->side);
+  (void)hipStreamDestroy(b->side);
+  (void)hipEventDestroy(b->ev_fork);
+  (void)hipEventDestroy(b->ev_join);
   delete b;
   return LBMDEM_OK;
 }
@@ -1186,16 +1213,19 @@ int32_t lbmdem_batch_step(lbmdem_batch* b, int32_t nsteps) {
   if (int32_t rc = build_tables(b)) return rc;
   if (b->t.ndom == 0 || nsteps == 0) return LBMDEM_OK;
   if (!b->use_graph) {
-    for (int s = 0; s < nsteps; ++s) launch_batch_step(b);
-    BHIPCHK(b, hipGetLastError());
+    for (int s = 0; s < nsteps; ++s) BHIPCHK(b, launch_batch_step(b));
     return LBMDEM_OK;
   }
   if (!b->exec) {
     BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    launch_batch_step(b);
+    const hipError_t el = launch_batch_step(b);
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (e != hipSuccess) return bfail(b, LBMDEM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (e == hipSuccess && el != hipSuccess) e = el;
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return bfail(b, LBMDEM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
     b->graph = g;
     BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }

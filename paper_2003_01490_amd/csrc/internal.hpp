@@ -271,7 +271,8 @@ void launch_fill_claims(const DevDomain& d, hipStream_t s);
 // batched step kernels over the domains of a batch
 void launch_sweep_batch(const BatchTables& b, hipStream_t s);
 void launch_dem_batch(const BatchTables& b, hipStream_t s);
-void launch_mapping_batch(const BatchTables& b, hipStream_t s);
+void launch_claim_batch(const BatchTables& b, hipStream_t s);
+void launch_update_batch(const BatchTables& b, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace lbmdem

@@ -1032,23 +1032,26 @@ __global__ __launch_bounds__(256) void k_commit_batch(const DevDomain* __restric
   commit_block<T>(d, (int)blockIdx.x - start[k], map_buffer(d.ctl, 1), map_stamp(d.ctl));
 }
 
-template <typename T>
-static void launch_mapping_batch_t(const BatchTables& b, hipStream_t s) {
-  if (b.claim_blocks > 0) {
+void launch_claim_batch(const BatchTables& b, hipStream_t s) {
+  if (b.claim_blocks > 0)
     hipLaunchKernelGGL(k_claim_batch, dim3(b.claim_blocks), dim3(256), 0, s, b.tab, b.claim_start, b.ndom);
+}
+
+template <typename T>
+static void launch_update_batch_t(const BatchTables& b, hipStream_t s) {
+  if (b.claim_blocks > 0)
     hipLaunchKernelGGL(k_recon_batch<T>, dim3(b.claim_blocks), dim3(256), 0, s, b.tab, b.claim_start, b.ndom);
-  }
   if (b.commit_blocks > 0)
     hipLaunchKernelGGL(k_commit_batch<T>, dim3(b.commit_blocks), dim3(256), 0, s, b.tab, b.commit_start, b.ndom);
 }
 
-void launch_mapping_batch(const BatchTables& b, hipStream_t s) {
+void launch_update_batch(const BatchTables& b, hipStream_t s) {
   if (b.storage == 0)
-    launch_mapping_batch_t<double>(b, s);
+    launch_update_batch_t<double>(b, s);
   else if (b.storage == 1)
-    launch_mapping_batch_t<float>(b, s);
+    launch_update_batch_t<float>(b, s);
   else
-    launch_mapping_batch_t<__half>(b, s);
+    launch_update_batch_t<__half>(b, s);
 }
 
 }  // namespace lbmdem

@@ -209,3 +209,34 @@ def test_dense_full_size_properties():
         assert np.array_equal(owner[K, J, I][sol], own[sol]), f"owners of sphere {i} box differ"
     print(f"  mapping of {len(sample)} sampled sphere boxes bit-exact", flush=True)
     g.close()
+
+
+@pytest.mark.timeout(300)
+def test_reduced_storage_128_against_fp64():
+    """The 128^3 sub-run of the FP16 precision variant (375 spheres D = 12,
+    16 % solids, 300 steps): FP32 and FP16 deviation storage against FP64
+    storage on the GPU, which the oracle pins to 1e-12 (test_dense_96_fp64;
+    tests/storage_error_report.py compares all three with the oracle itself).
+    FP32 is held to the acceptance bounds of the reduced-storage design
+    (|du|/|u| <= 1e-5, |dF|/|F| <= 1e-4); FP16 is reported, with loose bounds
+    against gross errors."""
+    wl = W.dense(0, n=128, count=375)
+    _case("dense 128^3, 375 spheres, FP64 / FP32 / FP16 storage, 300 steps")
+    res = {}
+    for storage in (0, 1, 2):
+        g = gpu_domain(wl, storage=storage)
+        g.step(300)
+        g.sync()
+        res[storage] = (g.field("vel"), g.spheres(), g.field("flags"))
+        g.close()
+    vel0, s0, fl0 = res[0]
+    fluid = fl0 <= 1
+    umax = np.sqrt((vel0 ** 2).sum(0))[fluid].max()
+    Fmax = np.linalg.norm(s0["F_fp"], axis=1).max()
+    for storage, (tol_u, tol_f, tol_x) in ((1, (1e-5, 1e-4, 1e-8)), (2, (0.1, 0.05, 1e-4))):
+        vel, s, _ = res[storage]
+        eu = float(np.sqrt(((vel - vel0) ** 2).sum(0))[fluid].max() / umax)
+        ef = float(np.linalg.norm(s["F_fp"] - s0["F_fp"], axis=1).max() / Fmax)
+        ex = float(np.abs(s["x"] - s0["x"]).max() / 12.0)
+        print(f"  storage {storage}: |du|/|u| {eu:.2e}  |dF|/|F| {ef:.2e}  |dx|/D {ex:.2e}", flush=True)
+        assert eu <= tol_u and ef <= tol_f and ex <= tol_x
