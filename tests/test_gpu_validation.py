@@ -63,3 +63,48 @@ def test_rebound_height_st27_matches_table():
     assert abs(s["u"][2]) < 1e-4  # at the apex
     assert abs(H_r - avg) <= 0.01 * avg
     dom.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("Re_s,steps", [(1, 30000), (25, 80000)])
+def test_shear_flow_drag_lift_matches_table(Re_s, steps):
+    """Fixed sphere (D_p = 20) one diameter above a resting wall in the shear
+    flow of a moving top wall (Sec. 2.5): domain 48 x 16 x 8 D_p, u_w = 0.1,
+    Re_s = G D_p^2 / nu, started from the linear shear profile at equilibrium.
+    Drag and lift coefficients of the resolved force against the TRT+aB
+    column of Tables drag_lift_sphere_Re1 / _Re25 (L = 1: 34.44 / 2.30 and
+    2.78 / 0.41), each within 1 % plus half a unit of the last printed digit.
+    This checks the moving-wall bounce-back, the CLI boundary, the momentum
+    exchange and TRT+aB together; ~1.5 ms per step on 49 M cells.  (For
+    L = 0.505 this build's coefficients follow the creeping-flow limit of a
+    sphere touching a wall -- F* = 1.70 -- and not the printed rows.)"""
+    import oracle as O
+    from paper_2003_01490_amd import lbmdem as L
+
+    case = [c for c in GOLD["shear_flow_sphere_near_wall"]["cases"] if c["Re_s"] == Re_s and c["L"] == 1.0][0]
+    D, uw, Lw = 20.0, 0.1, 1.0
+    H = 8 * D
+    nx, ny, nz = int(48 * D), int(16 * D), int(H) + 2
+    G = uw / H
+    p = W.base_params(nx=nx, ny=ny, nz=nz, walls=(0, 0, 1), wall_u_hi=(uw, 0.0, 0.0), nu=G * D * D / Re_s,
+                      max_spheres=1)
+    keys = {f[0] for f in L.Config._fields_}
+    cfg = L.default_config(**{k: v for k, v in p.items() if k in keys}, storage=L.STORE_F32, max_radius=D / 2)
+    print(f"[case] shear flow Re_s {Re_s}, L 1, {nx}x{ny}x{nz}, {steps} steps", flush=True)
+    dom = L.Domain(cfg, device="cuda:0")
+    z = np.arange(nz) + 0.5
+    feq = np.stack([O.equilibrium(1.0, (uw * (zz - 1.0) / H, 0.0, 0.0)) for zz in z], axis=1)
+    dom.set_pdf(np.broadcast_to(feq[:, :, None, None], (19, nz, ny, nx)))
+    dom.add_spheres(np.array([[24 * D, 8 * D, 1.0 + Lw * D]]), np.array([D / 2]), np.array([1.0]))
+    dom.set_mode(0, L.FIXED)
+    norm = np.pi / 8 * G * G * Lw * Lw * D ** 4
+    for k in range(0, steps, 10000):
+        dom.step(min(10000, steps - k))
+        dom.sync()
+        F = dom.sphere(0)["F_fp"]
+        print(f"  step {min(k + 10000, steps)} C_D {F[0] / norm:.4f} C_L {F[2] / norm:.4f}", flush=True)
+    cd, cl = F[0] / norm, F[2] / norm
+    print(f"  paper (TRT+aB): C_D {case['CD_trtab']} C_L {case['CL_trtab']}", flush=True)
+    assert abs(cd - case["CD_trtab"]) <= 0.01 * case["CD_trtab"] + 0.005
+    assert abs(cl - case["CL_trtab"]) <= 0.01 * case["CL_trtab"] + 0.005
+    dom.close()
