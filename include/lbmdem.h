@@ -114,6 +114,12 @@ typedef struct lbmdem_config {
                                waits on and rejoins the domain's stream within
                                the step.  0: everything on the domain's stream.
                                Results are identical.                             */
+  double body_force[3];     /* fluid body force a (force density, lattice units),
+                               Guo's forcing in the collision (test scenarios of
+                               Sec. 2.4 such as the Stokes-flow sphere array); it
+                               does not act on the spheres.  With a force the
+                               velocity read-out is sum f c - a/2 (the stored
+                               state is post-collision).  Default 0.            */
 } lbmdem_config;
 
 typedef struct lbmdem_domain lbmdem_domain;

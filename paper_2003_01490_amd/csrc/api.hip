@@ -176,6 +176,8 @@ const char* check_config(const lbmdem_config* c) {
   if (c->dem_kernel < 0 || c->dem_kernel > 2) return "dem_kernel must be 0..2";
   if (c->map_kernel < 0 || c->map_kernel > 2) return "map_kernel must be 0..2";
   if (c->overlap != 0 && c->overlap != 1) return "overlap must be 0 or 1";
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(c->body_force[a])) return "body_force must be finite";
   if (c->map_kernel == 2 && !ball_possible(*c))
     return "map_kernel 2 needs the staged cube (R_max + 4 cells each side) within 60000 bytes of LDS and "
            "within every periodic extent";
@@ -351,9 +353,11 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
     d.walls[a] = cfg->walls[a];
     d.wall_u_lo[a] = cfg->wall_u_lo[a];
     d.wall_u_hi[a] = cfg->wall_u_hi[a];
+    d.force[a] = cfg->body_force[a];
     d.gravity[a] = cfg->gravity[a];
   }
   d.storage = cfg->storage;
+  d.forced = (cfg->body_force[0] != 0.0 || cfg->body_force[1] != 0.0 || cfg->body_force[2] != 0.0) ? 1 : 0;
   d.boundary = cfg->boundary;
   // Eq. (Viscosity), Eq. (MagicParameter), Eq. (lambda_b)
   const double snu = 1.0 / (3.0 * cfg->nu + 0.5);
@@ -843,7 +847,7 @@ bool same_config(const lbmdem_config& a, const lbmdem_config& b) {
             a.max_spheres == b.max_spheres && a.dem_kernel == b.dem_kernel && a.map_kernel == b.map_kernel;
   for (int k = 0; k < 3; ++k)
     eq = eq && a.walls[k] == b.walls[k] && a.wall_u_lo[k] == b.wall_u_lo[k] && a.wall_u_hi[k] == b.wall_u_hi[k] &&
-         a.gravity[k] == b.gravity[k];
+         a.gravity[k] == b.gravity[k] && a.body_force[k] == b.body_force[k];
   eq = eq && a.nu == b.nu && a.magic_lambda == b.magic_lambda && a.lambda_b == b.lambda_b &&
        a.delta_ab == b.delta_ab && a.e_dry == b.e_dry && a.poisson_ratio == b.poisson_ratio &&
        a.friction == b.friction && a.tc == b.tc && a.dmin == b.dmin && a.cut_n == b.cut_n &&

@@ -64,7 +64,10 @@ __global__ void k_get_plane(DevDomain d, int which, double* dst) {
           const int cq = which == 0 ? 1 : (which == 1 ? CX[q] : (which == 2 ? CY[q] : CZ[q]));
           s += g * cq;
         }
-        v = which == 0 ? 1.0 + s : s;
+        // with a body force the stored (post-collision) momentum holds the
+        // whole impulse a; the velocity is half-way
+        const double a = which == 1 ? d.force[0] : (which == 2 ? d.force[1] : d.force[2]);
+        v = which == 0 ? 1.0 + s : s - 0.5 * a;
       }
     }
     dst[c] = v;

@@ -120,6 +120,8 @@ struct DevDomain {
   long long N;
   int walls[3];
   double wall_u_lo[3], wall_u_hi[3];
+  double force[3];  // fluid body force (Guo forcing)
+  int forced;       // force != 0
   int storage;     // 0 f64, 1 f32, 2 f16
   int boundary;    // 0 CLI, 1 BB
   double s_plus, s_minus, s_bulk_shell, s_bulk_other;

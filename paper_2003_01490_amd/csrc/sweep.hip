@@ -92,7 +92,15 @@ struct Store<__half> {
   WALL_BB(16, 11, W2, 0, -1, -1, ux, uy, uz); WALL_BB(17, 14, W2, -1, 0, -1, ux, uy, uz); \
   WALL_BB(18, 13, W2, 1, 0, -1, ux, uy, uz)
 
-template <typename T>
+// FORCED: a fluid body force a by Guo's scheme, written in velocity space:
+// the equilibrium takes u = j + a/2, and the collision adds
+// (1 - s+/2) F+ + (1 - s-/2) F- with F+_q = w_q (9 (c.u)(c.a) - 3 u.a) and
+// F-_q = 3 w_q c.a (the even and odd parts of Guo's source term); of the two
+// bulk rows only the kinetic-energy row sees F+ (M_4 . F+ = 2 u.a, M_5 . F+ =
+// 0), which adds -3/2 (s_b - s+) u.a to that row's correction.  On the
+// conserved momentum TRT's odd rate and the moment-space rate 0 give the same
+// j + a.
+template <typename T, bool FORCED>
 __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restrict__ src, T* __restrict__ dst,
                                            int x, int y, int z, typename Store<T>::C sp,
                                            typename Store<T>::C sm, typename Store<T>::C db_shell,
@@ -158,16 +166,26 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
                  ((g[15] + g[16]) + (g[17] + g[18]));
   const C suma = ((g[1] + g[2]) + (g[3] + g[4])) + (g[5] + g[6]);
   const C rho = (g[0] + suma) + sumd;  // rho - 1
-  const C ux = ((g[4] - g[3]) + (g[8] - g[7])) + ((g[10] - g[9]) + (g[14] - g[13])) + (g[18] - g[17]);
-  const C uy = ((g[1] - g[2]) + (g[7] + g[8])) - ((g[9] + g[10]) - (g[11] - g[12])) + (g[15] - g[16]);
-  const C uz = ((g[5] - g[6]) + (g[11] + g[12])) + ((g[13] + g[14]) - (g[15] + g[16])) - (g[17] + g[18]);
+  C ux = ((g[4] - g[3]) + (g[8] - g[7])) + ((g[10] - g[9]) + (g[14] - g[13])) + (g[18] - g[17]);
+  C uy = ((g[1] - g[2]) + (g[7] + g[8])) - ((g[9] + g[10]) - (g[11] - g[12])) + (g[15] - g[16]);
+  C uz = ((g[5] - g[6]) + (g[11] + g[12])) + ((g[13] + g[14]) - (g[15] + g[16])) - (g[17] + g[18]);
+  C ax = C(0), ay = C(0), az = C(0), ua = C(0);
+  if (FORCED) {
+    ax = (C)d.force[0];
+    ay = (C)d.force[1];
+    az = (C)d.force[2];
+    ux += C(0.5) * ax;
+    uy += C(0.5) * ay;
+    uz += C(0.5) * az;
+    ua = ux * ax + uy * ay + uz * az;
+  }
   const C usq = ux * ux + uy * uy + uz * uz;
 
   // bulk correction amplitudes (rows 4 and 5 of M, 0-based)
   const C db = (fl & F_SHELL) ? db_shell : db_other;  // s_b - s+
   const C m4 = sumd - g[0];
   const C m5 = (g[0] - C(2) * suma) + sumd;
-  const C A4 = db * (C(1.5) * (usq - m4));
+  const C A4 = db * (C(1.5) * (FORCED ? (usq - m4) - ua : usq - m4));
   const C A5 = db * (C(-0.5) * m5);
 
   const C w0 = C(1.0 / 3.0), w1 = C(1.0 / 18.0), w2 = C(1.0 / 36.0);
@@ -203,6 +221,29 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
   PAIR(14, 17, w2, base2, ux + uz, bd)
 #undef PAIR
 
+  if (FORCED) {
+    const C cp = C(1) - C(0.5) * sp, cm = C(1) - C(0.5) * sm;
+    o[0] += cp * (w0 * (C(-3) * ua));
+#define FPAIR(a, b, w, cu, ca)                                 \
+  {                                                            \
+    const C ca_ = (ca);                                        \
+    const C fp = cp * ((w) * (C(9) * (cu) * ca_ - C(3) * ua)); \
+    const C fm = cm * ((w) * (C(3) * ca_));                    \
+    o[a] += fp + fm;                                           \
+    o[b] += fp - fm;                                           \
+  }
+    FPAIR(1, 2, w1, uy, ay)
+    FPAIR(4, 3, w1, ux, ax)
+    FPAIR(5, 6, w1, uz, az)
+    FPAIR(7, 10, w2, uy - ux, ay - ax)
+    FPAIR(8, 9, w2, ux + uy, ax + ay)
+    FPAIR(11, 16, w2, uy + uz, ay + az)
+    FPAIR(12, 15, w2, uz - uy, az - ay)
+    FPAIR(13, 18, w2, uz - ux, az - ax)
+    FPAIR(14, 17, w2, ux + uz, ax + az)
+#undef FPAIR
+  }
+
 #pragma unroll
   for (int q = 0; q < Q; ++q) Store<T>::store(dst + (size_t)q * NN + idx, o[q]);
 }
@@ -216,7 +257,7 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
 
 // one domain: whole x-rows per block (see launch_sweep_t); the current buffer
 // is read from the domain's step state
-template <typename T>
+template <typename T, bool FORCED>
 __global__ __launch_bounds__(256) void k_sweep(DevDomain d) {
   using C = typename Store<T>::C;
   if (!step_live(d.ctl)) return;
@@ -228,8 +269,8 @@ __global__ __launch_bounds__(256) void k_sweep(DevDomain d) {
   // place the whole descriptor in scratch memory)
   const T* src = (const T*)(cur ? d.pdf[1] : d.pdf[0]);
   T* dst = (T*)(cur ? d.pdf[0] : d.pdf[1]);
-  sweep_cell<T>(d, src, dst, x, y, blockIdx.z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
-                (C)(d.s_bulk_other - d.s_plus));
+  sweep_cell<T, FORCED>(d, src, dst, x, y, blockIdx.z, (C)d.s_plus, (C)d.s_minus,
+                        (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
 }
 
 // many domains in one launch: block b belongs to the domain k with
@@ -247,8 +288,12 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const DevDomain* __restrict
   const int cur = d.ctl->cur;
   const T* src = (const T*)d.pdf[cur];
   T* dst = (T*)d.pdf[cur ^ 1];
-  sweep_cell<T>(d, src, dst, x, y, z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
-                (C)(d.s_bulk_other - d.s_plus));
+  if (d.forced)  // uniform over the block (one domain)
+    sweep_cell<T, true>(d, src, dst, x, y, z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
+                        (C)(d.s_bulk_other - d.s_plus));
+  else
+    sweep_cell<T, false>(d, src, dst, x, y, z, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
+                         (C)(d.s_bulk_other - d.s_plus));
 }
 
 template <typename T>
@@ -273,7 +318,10 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
   grid.x = (d.nx + block.x - 1) / block.x;
   grid.y = (d.ny + block.y - 1) / block.y;
   grid.z = d.nz;
-  hipLaunchKernelGGL(k_sweep<T>, grid, block, 0, s, d);
+  if (d.forced)
+    hipLaunchKernelGGL((k_sweep<T, true>), grid, block, 0, s, d);
+  else
+    hipLaunchKernelGGL((k_sweep<T, false>), grid, block, 0, s, d);
 }
 
 void launch_sweep(const DevDomain& d, hipStream_t s) {

@@ -51,6 +51,7 @@ class Config(C.Structure):
         ("dem_kernel", C.c_int32),
         ("map_kernel", C.c_int32),
         ("overlap", C.c_int32),
+        ("body_force", C.c_double * 3),
     ]
 
 

@@ -64,6 +64,41 @@ def test_fluid_only_periodic_random_pdf(coll):
     _compare_fields(g, o)
 
 
+@pytest.mark.parametrize("coll", [O.TRT_AB, O.TRT_B, O.SRT])
+def test_body_force_fluid_and_fixed_sphere(coll):
+    """Guo forcing (the oracle's moment-space form against the sweep's
+    velocity-space form): a periodic random field under a body force, then a
+    fixed sphere in it (momentum exchange and the shell under forcing)."""
+    n = (17, 12, 16)
+    a = (2e-5, -1e-5, 3e-5)
+    _case(f"body force {a} on {n}, collision {coll}")
+    wl = W.Workload("forced", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 0), nu=0.03,
+                                            collision=coll, max_spheres=1, body_force=a),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    f = random_pdf(n, seed=11 + coll, u0=(0.01, 0.0, -0.005))
+    o = oracle_domain(wl)
+    g = gpu_domain(wl)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(10)
+    g.step(10)
+    _compare_fields(g, o)
+    wl.x, wl.R, wl.rho = np.array([[8.3, 6.1, 7.7]]), np.array([3.2]), np.array([1.0])
+    wl.u, wl.w = np.zeros((1, 3)), np.zeros((1, 3))
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    o.set_mode(0, O.MODE_FIXED)
+    from paper_2003_01490_amd import lbmdem as L
+    g.set_mode(0, L.FIXED)
+    for _ in range(4):
+        o.step(15)
+        g.step(15)
+        so, sg = o.sphere(0), g.sphere(0)
+        Fs = max(np.abs(so["F_raw"]).max(), 1e-300)
+        assert np.abs(sg["F_raw"] - so["F_raw"]).max() <= 1e-10 * Fs
+        assert np.abs(sg["T_raw"] - so["T_raw"]).max() <= 1e-10 * Fs * 3.2
+    _compare_fields(g, o)
+
+
 def test_couette_channel_and_moving_walls():
     n = (8, 6, 14)
     _case(f"couette {n}")
