@@ -200,6 +200,13 @@ int32_t lbmdem_get_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, do
 int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t bytes,
                          int32_t dst_is_device);
 
+/* Synchronising probe: the density at n points (host xyz[3n], lattice units;
+ * cell centres at i + 1/2) by trilinear interpolation of the cell-centre
+ * densities of the current state, into out[n] (host).  A point whose eight
+ * surrounding cells are not all fluid, or that lies beyond a wall layer,
+ * reads NaN.  At most N/4 points per call (LBMDEM_EINVAL beyond). */
+int32_t lbmdem_probe_density(lbmdem_domain* dom, int32_t n, const double* xyz, double* out);
+
 /* Overwrites all PDFs with the full distributions f (host, double[19N],
  * q-major), rounded to the storage precision, and recomputes the boundary
  * values of the next step. */

@@ -762,6 +762,20 @@ int32_t lbmdem_get_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, do
   return LBMDEM_OK;
 }
 
+int32_t lbmdem_probe_density(lbmdem_domain* dom, int32_t n, const double* xyz, double* out) {
+  if (!dom || n < 0 || (n > 0 && (!xyz || !out))) return LBMDEM_EINVAL;
+  if ((size_t)n * 4 > (size_t)dom->d.N) return fail(dom, LBMDEM_EINVAL, "too many probe points (at most N/4)");
+  if (n == 0) return LBMDEM_OK;
+  double* stage = (double*)((char*)dom->region + dom->L.stage);
+  hipStream_t st = dom->stream;
+  HIPCHK(dom, hipMemcpyAsync(stage, xyz, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+  launch_probe_density(dom->d, stage, n, st);
+  HIPCHK(dom, hipGetLastError());
+  HIPCHK(dom, hipMemcpyAsync(out, stage + 3 * (size_t)n, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(dom, hipStreamSynchronize(st));
+  return LBMDEM_OK;
+}
+
 int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t bytes,
                          int32_t dst_is_device) {
   if (!dom || !dst) return LBMDEM_EINVAL;

@@ -105,6 +105,60 @@ __global__ void k_copy1(uint8_t* dst, const uint8_t* src, size_t n) {
     dst[i] = src[i];
 }
 
+// Density at points (xyz[3n], lattice units) by trilinear interpolation of
+// the cell-centre densities of the current state (periodic axes wrap); NaN
+// when one of the eight cells is not fluid or lies outside a walled axis.
+// Buffer io: the 3n coordinates, then the n results.
+template <typename T>
+__global__ void k_probe_density(DevDomain d, double* io, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const size_t N = (size_t)d.N;
+  const T* f = (const T*)(d.ctl->cur ? d.pdf[1] : d.pdf[0]);
+  const int nn[3] = {d.nx, d.ny, d.nz};
+  int i0[3];
+  double t[3];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double s = io[3 * k + a] - 0.5;
+    const double fl = floor(s);
+    i0[a] = (int)fl;
+    t[a] = s - fl;
+    if (d.walls[a]) ok = ok && i0[a] >= 0 && i0[a] + 1 < nn[a];
+  }
+  double r = 0.0;
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      int ijk[3];
+      double w = 1.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int o = (c >> a) & 1;
+        ijk[a] = d.walls[a] ? i0[a] + o : wrapmod(i0[a] + o, nn[a]);
+        w *= o ? t[a] : 1.0 - t[a];
+      }
+      const size_t cc = (size_t)cidx(d, ijk[0], ijk[1], ijk[2]);
+      if (d.flags[cc] & (F_SOLID | F_WALL)) ok = false;
+      double rho = 1.0;
+      for (int q = 0; q < Q; ++q) rho += to_d<T>(f[(size_t)q * N + cc]);
+      r += w * rho;
+    }
+  }
+  io[3 * (size_t)n + k] = ok ? r : __builtin_nan("");
+}
+
+void launch_probe_density(const DevDomain& d, double* io, int n, hipStream_t s) {
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (d.storage == 0)
+    hipLaunchKernelGGL(k_probe_density<double>, g, dim3(256), 0, s, d, io, n);
+  else if (d.storage == 1)
+    hipLaunchKernelGGL(k_probe_density<float>, g, dim3(256), 0, s, d, io, n);
+  else
+    hipLaunchKernelGGL(k_probe_density<__half>, g, dim3(256), 0, s, d, io, n);
+}
+
 static dim3 grid_for(size_t n) {
   size_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;

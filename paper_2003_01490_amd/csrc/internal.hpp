@@ -269,6 +269,8 @@ constexpr int DEM_GRID_THREADS = 128;
 constexpr int DEM_GRID_MIN = 256;
 void launch_fields(const DevDomain& d, int field, double* dst, hipStream_t s);
 void launch_set_pdf(const DevDomain& d, int q, const double* src, hipStream_t s);
+// densities at n points: io holds 3n coordinates, then receives n results
+void launch_probe_density(const DevDomain& d, double* io, int n, hipStream_t s);
 void launch_fill_claims(const DevDomain& d, hipStream_t s);
 // batched step kernels over the domains of a batch
 void launch_sweep_batch(const BatchTables& b, hipStream_t s);

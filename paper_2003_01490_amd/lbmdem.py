@@ -104,6 +104,7 @@ def lib():
         "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
         "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
         "lbmdem_sweep_bytes": (C.c_double, [vp]),
+        "lbmdem_probe_density": (C.c_int32, [vp, C.c_int32, dp, dp]),
         "lbmdem_device_copy": (C.c_int32, [vp, vp, C.c_size_t, vp]),
         "lbmdem_last_error": (C.c_char_p, [vp]),
     }
@@ -310,6 +311,14 @@ class Domain:
 
     def flags(self):
         return self.field("flags"), self.field("owner")
+
+    def probe_density(self, xyz) -> np.ndarray:
+        """Densities at points (n, 3) by trilinear interpolation (NaN where a
+        surrounding cell is not fluid)."""
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        out = np.empty(len(xyz))
+        self._check(lib().lbmdem_probe_density(self.h, len(xyz), _dp(xyz), _dp(out)))
+        return out
 
     def set_pdf(self, f):
         f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(19 * self.N))

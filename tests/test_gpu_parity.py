@@ -99,6 +99,38 @@ def test_body_force_fluid_and_fixed_sphere(coll):
     _compare_fields(g, o)
 
 
+def test_density_probe_against_oracle_field():
+    """lbmdem_probe_density: trilinear interpolation of the cell-centre
+    densities, against the same interpolation of the oracle's density field
+    (FP64 storage, settling workload after 60 steps), NaN next to solid or
+    wall cells."""
+    wl = W.settling_32(0)
+    _case("density probe, settling_32 after 60 steps")
+    o, g = oracle_domain(wl), gpu_domain(wl)
+    o.step(60)
+    g.step(60)
+    rho = o.field("rho")  # (nz, ny, nx)
+    code = o.flags()[0]
+    rng = np.random.default_rng(5)
+    pts = np.column_stack([rng.uniform(0, 32, 200), rng.uniform(0, 32, 200), rng.uniform(1.5, 30.5, 200)])
+    got = g.probe_density(pts)
+    for p, v in zip(pts, got):
+        s = p - 0.5
+        i0 = np.floor(s).astype(int)
+        t = s - i0
+        ref, fluid = 0.0, True
+        for c in range(8):
+            o3 = [(c >> a) & 1 for a in range(3)]
+            ii = [(i0[0] + o3[0]) % 32, (i0[1] + o3[1]) % 32, i0[2] + o3[2]]
+            w = np.prod([t[a] if o3[a] else 1 - t[a] for a in range(3)])
+            fluid = fluid and code[ii[2], ii[1], ii[0]] <= O.SHELL
+            ref += w * rho[ii[2], ii[1], ii[0]]
+        if fluid:
+            assert abs(v - ref) <= 1e-12, (p, v, ref)
+        else:
+            assert np.isnan(v), (p, v)
+
+
 def test_couette_channel_and_moving_walls():
     n = (8, 6, 14)
     _case(f"couette {n}")

@@ -148,3 +148,53 @@ def test_stokes_array_drag_matches_reference_on_gpu():
     assert abs(c1 / cref - 1) < 5e-3 and abs(c2 / cref - 1) < 5e-3
     assert abs(c1 - c2) < 2e-3 * cref
     assert abs(cs / cref - 1) > 0.03
+
+
+@pytest.mark.timeout(600)
+def test_bulk_viscosity_damps_density_fluctuations():
+    """Density fluctuations at a probe moving with a prescribed sphere (Sec.
+    2.3.3: [4 x 4 x 8] D_p with walls in x and y, periodic in z, D_p = 20,
+    u_p = -u_s (1 - exp(-c_acc t / t_St)) with u_s = 0.02, c_acc = 10,
+    rho_p / rho_f = 8.34, Re = 164, probe at x_p + (D_p, 0, 0) by trilinear
+    interpolation, 24 t_ref = 24,000 steps).  The fluctuation signal is the
+    density minus its moving average over one t_ref (the slow drift of the
+    mean density, from the non-conserving mapping updates, is removed).  The
+    paper shows the damping only as a spectrum; checked here: the fluctuations
+    fall as the bulk viscosity grows (TRT > TRT+B(10) > TRT+B(100)), the
+    adaptive shell (TRT+aB) damps them below TRT, and with TRT+aB and
+    TRT+B(100) they stay below the paper's bound of 0.01 % of the mean
+    density."""
+    from paper_2003_01490_amd import lbmdem as L
+
+    D, us, Re, rho_r, c_acc = 20.0, 0.02, 164.0, 8.34, 10.0
+    nu = us * D / Re
+    nxy, nz = int(4 * D) + 2, int(8 * D)
+    steps, every, win = 24000, 2, 501
+    hp = {}
+    for name, coll, lb in (("TRT", L.TRT_B, 1.0), ("TRT+B10", L.TRT_B, 10.0), ("TRT+B100", L.TRT_B, 100.0),
+                           ("TRT+aB", L.TRT_AB, 100.0)):
+        p = W.base_params(nx=nxy, ny=nxy, nz=nz, walls=(1, 1, 0), nu=nu, collision=coll, lambda_b=lb,
+                          max_spheres=1)
+        keys = {f[0] for f in L.Config._fields_}
+        cfg = L.default_config(**{k: v for k, v in p.items() if k in keys}, storage=L.STORE_F32,
+                               max_radius=D / 2)
+        print(f"[case] E1 {name}, {nxy}x{nxy}x{nz}, {steps} steps", flush=True)
+        dom = L.Domain(cfg, device="cuda:0")
+        dom.add_spheres(np.array([[1.0 + 2 * D, 1.0 + 2 * D, 4 * D]]), np.array([D / 2]), np.array([rho_r]))
+        dom.set_mode(0, L.PRESCRIBED, (0.0, 0.0, -us), c_acc, rho_r * D * D / (18 * nu), D)
+        sig = []
+        for _ in range(0, steps, every):
+            dom.step(every)
+            xs = dom.sphere(0)["x"]
+            sig.append(dom.probe_density(np.array([[xs[0] + D, xs[1], xs[2]]]))[0])
+        dom.close()
+        sig = np.array(sig)
+        assert np.isfinite(sig).all()
+        smooth = np.convolve(sig, np.ones(win) / win, mode="same")
+        h = (sig - smooth)[win:-win]
+        hp[name] = (float(np.abs(h).max()), float(h.std()))
+        print(f"  {name}: fluctuation max {hp[name][0]:.2e} std {hp[name][1]:.2e} "
+              f"(mean density {sig.mean():.6f})", flush=True)
+    assert hp["TRT"][1] > hp["TRT+B10"][1] > hp["TRT+B100"][1]
+    assert hp["TRT+aB"][1] < hp["TRT"][1]
+    assert hp["TRT+aB"][0] < 1e-4 and hp["TRT+B100"][0] < 1e-4
