@@ -210,6 +210,7 @@ struct lbmdem_domain {
   double ms[3] = {0, 0, 0};
   int64_t cnt[3] = {0, 0, 0};
   lbmdem_batch* batch = nullptr;      // batch the domain is admitted to
+  bool may_prescribe = false;         // a sphere was given prescribed motion (or state restored)
   // second stream of an overlapped step (created on first use) and the events
   // that fork it from and join it to the domain's stream
   hipStream_t side = nullptr;
@@ -613,6 +614,7 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode, con
   HIPCHK(dom, hipMemcpyAsync(p.mode + id, &mode, 4, hipMemcpyHostToDevice, st));
   HIPCHK(dom, hipMemcpyAsync(p.old_valid + id, &zero, 4, hipMemcpyHostToDevice, st));
   if (mode == LBMDEM_PRESCRIBED) {
+    dom->may_prescribe = true;
     const double pr[6] = {u_target[0], u_target[1], u_target[2], c_acc, t_st, release_gap};
     const double z3[3] = {0, 0, 0};
     const double t0 = 0.0;
@@ -661,7 +663,7 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
     }
     auto dem = [&] {
       timed(dom, 1, ds, [&] {
-        e = launch_dem(dom->d, dom->cfg.dem_kernel, ds);
+        e = launch_dem(dom->d, dom->cfg.dem_kernel, !dom->may_prescribe, ds);
         launch_claim(dom->d, 1, ds);
       });
     };
@@ -959,6 +961,7 @@ int32_t lbmdem_restore(lbmdem_domain* dom, const void* host_blob, size_t bytes) 
   }
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
   dom->d.P = h.P;
+  dom->may_prescribe = true;  // the restored spheres' modes are not known here
   dom->failed = 0;
   return LBMDEM_OK;
 }

@@ -734,8 +734,13 @@ __global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_position(DevDomain d,
 
 // forces at the new positions with the old velocities, new velocities into
 // the other buffer; after the last sub-cycle the state is copied back if it
-// ended in the second buffers (odd n_sub, a kernel of its own) and checked
-__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_velocity(DevDomain d, int sub) {
+// ended in the second buffers (odd n_sub, a kernel of its own) and checked.
+// With `fuse` the thread then advances its own sphere's position of the next
+// sub-cycle: nothing in this launch reads the buffer that goes into, and that
+// step reads only the sphere's own state -- valid when no sphere can be
+// released from a prescribed motion (a release evaluates forces on every
+// partner's state, which needs the sub-cycle's launch boundary).
+__global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_velocity(DevDomain d, int sub, int fuse) {
   if (dem_stopped(d)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.P) return;
@@ -748,6 +753,12 @@ __global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_velocity(DevDomain d,
   eval_forces(d, b, i, true, true, dtp, d.p.Fnew + 6 * i, d.p.Fnew + 6 * i + 3);
   advance_velocity(d, b, i, dtp, u1 + 3 * i, w1 + 3 * i);
   if (sub == d.n_sub - 1 && !(d.n_sub & 1)) health_check(d, d.p, i);
+  if (fuse) {
+    DevParticles n;
+    double *xn, *un, *wn;
+    subcycle_buffers(d.p, sub + 1, n, &xn, &un, &wn);
+    advance_position(d, n, i, dtp, xn + 3 * i);
+  }
 }
 
 __global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_epilogue(DevDomain d) {
@@ -765,7 +776,7 @@ __global__ __launch_bounds__(DEM_GRID_THREADS) void k_demg_epilogue(DevDomain d)
 
 bool dem_many(const DevDomain& d, int kernel) { return kernel == 2 || (kernel == 0 && d.P > DEM_GRID_MIN); }
 
-hipError_t launch_dem(const DevDomain& d, int kernel, hipStream_t s) {
+hipError_t launch_dem(const DevDomain& d, int kernel, bool no_release, hipStream_t s) {
   if (d.P <= 0) return hipSuccess;
   if (!dem_many(d, kernel)) {
     if (d.P <= DEM_LDS_MAX)
@@ -778,9 +789,11 @@ hipError_t launch_dem(const DevDomain& d, int kernel, hipStream_t s) {
   const unsigned blocks = (unsigned)((d.P + T - 1) / T);
   hipLaunchKernelGGL(k_demg_prologue, dim3((unsigned)(((long long)d.P * 64 + T - 1) / T)), dim3(T), 0, s, d);
   hipLaunchKernelGGL(k_demg_neighbours, dim3(blocks), dim3(T), 0, s, d);
+  hipLaunchKernelGGL(k_demg_position, dim3(blocks), dim3(T), 0, s, d, 0);
   for (int sub = 0; sub < d.n_sub; ++sub) {
-    hipLaunchKernelGGL(k_demg_position, dim3(blocks), dim3(T), 0, s, d, sub);
-    hipLaunchKernelGGL(k_demg_velocity, dim3(blocks), dim3(T), 0, s, d, sub);
+    const int fuse = no_release && sub + 1 < d.n_sub ? 1 : 0;
+    hipLaunchKernelGGL(k_demg_velocity, dim3(blocks), dim3(T), 0, s, d, sub, fuse);
+    if (!fuse && sub + 1 < d.n_sub) hipLaunchKernelGGL(k_demg_position, dim3(blocks), dim3(T), 0, s, d, sub + 1);
   }
   if (d.n_sub & 1) hipLaunchKernelGGL(k_demg_epilogue, dim3(blocks), dim3(T), 0, s, d);
   return hipGetLastError();

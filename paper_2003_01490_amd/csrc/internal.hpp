@@ -260,8 +260,10 @@ void launch_update_and_advance(const DevDomain& d, hipStream_t s);
 void launch_advance(const DevDomain& d, hipStream_t s);
 void launch_advance_batch(const BatchTables& b, hipStream_t s);
 // DEM sub-cycles.  kernel: 0 automatic, 1 single workgroup, 2 one thread per
-// sphere over a chain of launches (binned neighbour search).
-hipError_t launch_dem(const DevDomain& d, int kernel, hipStream_t s);
+// sphere over a chain of launches (binned neighbour search).  no_release: no
+// sphere is in (or can leave) prescribed motion, which lets the chain merge
+// each sub-cycle's position update into the previous velocity launch.
+hipError_t launch_dem(const DevDomain& d, int kernel, bool no_release, hipStream_t s);
 // whether launch_dem takes the many-sphere chain
 bool dem_many(const DevDomain& d, int kernel);
 constexpr int DEM_GRID_THREADS = 128;
