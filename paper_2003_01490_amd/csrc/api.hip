@@ -1,6 +1,7 @@
 // Host side of the lbmdem C-ABI: configuration checks, the layout of the
 // caller-owned device region, sphere management, step orchestration on the
 // domain's stream, read-out and profiling.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -96,7 +97,7 @@ void bin_dims(const lbmdem_config& c, int* nb) {
 struct Layout {
   size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
-      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, bins, ctl, partial, status;
+      old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, order, bins, ctl, partial, status;
   size_t total;
 };
 
@@ -144,6 +145,7 @@ Layout make_layout(const lbmdem_config& c) {
   L.x2 = take(24 * P);
   L.u2 = take(24 * P);
   L.w2 = take(24 * P);
+  L.order = take(4 * P);
   int nb[3];
   bin_dims(c, nb);
   L.bins = take(4 * (size_t)nb[0] * nb[1] * nb[2] * (1 + BIN_CAP));
@@ -274,8 +276,48 @@ static void timed(lbmdem_domain* dom, int kind, hipStream_t s, F&& launch) {
   if (ev.a && ev.b) dom->pending.push_back(ev);
 }
 
+static int32_t refresh_host_positions(lbmdem_domain* dom);
+
+static uint64_t spread21(uint64_t v) {
+  v &= 0x1FFFFF;
+  v = (v | v << 32) & 0x1F00000000FFFFull;
+  v = (v | v << 16) & 0x1F0000FF0000FFull;
+  v = (v | v << 8) & 0x100F00F00F00F00Full;
+  v = (v | v << 4) & 0x10C30C30C30C30C3ull;
+  v = (v | v << 2) & 0x1249249249249249ull;
+  return v;
+}
+
+// Order in which the sphere-centric boundary pass takes the spheres: by the
+// Morton (Z-order) code of the cell holding the centre, so that spheres close
+// in the order are close in space.  It only affects speed: every order gives
+// the same results.  Refreshed whenever the mapping is rebuilt from the host.
+static int32_t refresh_order(lbmdem_domain* dom) {
+  const size_t P = dom->hR.size();
+  if (!P) return LBMDEM_OK;
+  if (int32_t rc = refresh_host_positions(dom)) return rc;
+  const int n[3] = {dom->cfg.nx, dom->cfg.ny, dom->cfg.nz};
+  std::vector<std::pair<uint64_t, int>> key(P);
+  for (size_t i = 0; i < P; ++i) {
+    uint64_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double v = dom->hx[3 * i + a];
+      const int c = std::isfinite(v) ? std::min(std::max((int)std::floor(v), 0), n[a] - 1) : 0;
+      code |= spread21((uint64_t)c) << a;
+    }
+    key[i] = {code, (int)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> ord(P);
+  for (size_t i = 0; i < P; ++i) ord[i] = key[i].second;
+  HIPCHK(dom, hipMemcpyAsync(dom->d.p.order, ord.data(), 4 * P, hipMemcpyHostToDevice, dom->stream));
+  HIPCHK(dom, hipStreamSynchronize(dom->stream));
+  return LBMDEM_OK;
+}
+
 static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
   dom->d.P = (int)dom->hR.size();
+  if (int32_t rc = refresh_order(dom)) return rc;
   timed(dom, 2, dom->stream, [&] { launch_mapping(dom->d, reconstruct, dom->stream); });
   HIPCHK(dom, hipGetLastError());
   return LBMDEM_OK;
@@ -408,6 +450,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   p.x2 = (double*)(base + L.x2);
   p.u2 = (double*)(base + L.u2);
   p.w2 = (double*)(base + L.w2);
+  p.order = (int*)(base + L.order);
   bin_dims(*cfg, d.bins.n);
   d.bins.cell = (int*)(base + L.bins);
   d.ctl = (DevCtl*)(base + L.ctl);
@@ -843,7 +886,7 @@ int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
 namespace {
 
 constexpr char CK_MAGIC[8] = {'L', 'B', 'M', 'D', 'E', 'M', 'C', 'K'};
-constexpr uint32_t CK_VERSION = 2;
+constexpr uint32_t CK_VERSION = 3;
 
 struct CkHeader {
   char magic[8];

@@ -106,6 +106,7 @@ struct DevParticles {
   double* x2;     // [P][3] second buffers of x, u, w: the many-sphere DEM
   double* u2;     //        kernel alternates between the two every sub-cycle
   double* w2;
+  int* order;     // [P] sphere ids in space-filling-curve order of their centres
 };
 
 // uniform bins of the many-sphere neighbour search: edge >= the largest centre
@@ -185,6 +186,15 @@ struct BatchTables {
   int sweep_blocks, claim_blocks, commit_blocks;
   int storage;
 };
+
+// The hardware hands workgroups to the eight XCDs round-robin by id.  Block
+// w of a grid of G blocks (G a multiple of 8) takes tile (w mod 8) G/8 + w/8:
+// each XCD works through one contiguous eighth of the tiles, in order, so
+// tiles that share cache lines (neighbouring row pieces, spheres that are
+// close in the order) are served by the same L2.
+constexpr int XCDS = 8;
+__device__ __forceinline__ int xcd_tile(int w, int G) { return (w & (XCDS - 1)) * (G / XCDS) + w / XCDS; }
+inline int xcd_grid(int tiles) { return (tiles + XCDS - 1) / XCDS * XCDS; }
 
 // domain of block b: the k with start[k] <= b < start[k+1] (binary search)
 __device__ __forceinline__ int batch_domain(const int* start, int ndom, int b) {

@@ -1,9 +1,10 @@
 // Fused D3Q19 pull stream + TRT+aB collide (Eqs. LBM_Stream, LBM_Collide, MRT
 // with the rates of Eqs. TRTmatrix / TRTbulkmatrix, adaptive shell of Sec. 2.3.2).
 //
-// One thread per cell, one block per whole x-row group, so that the +-1
-// x-shifted loads of a row stay inside the block and every source value is
-// fetched from HBM once.  The PDF slots of solid cells carry the boundary
+// One thread per cell, one block per whole x-row group where rows are at most
+// 256 cells, so that the +-1 x-shifted loads of a row stay inside the block
+// and every source value is fetched from HBM once (wider rows are split into
+// pieces; the x-shifted loads then fetch one shared line per piece twice).  The PDF slots of solid cells carry the boundary
 // values of the particle links that stream out of them (written by the
 // boundary kernel), so a fluid cell pulls 19 values without branching.  Wall
 // layers are fixed, so the sweep knows from the cell's coordinates which
@@ -255,21 +256,26 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
 #undef WALLS_ZP
 #undef WALLS_ZM
 
-// one domain: whole x-rows per block (see launch_sweep_t); the current buffer
-// is read from the domain's step state
+// one domain: tiles of whole x-rows, or of row pieces on wide lattices (see
+// launch_sweep_t), gx x gy tiles per z plane, x fastest; with `chunk` each
+// XCD takes a contiguous run of tiles; the current buffer is read from the
+// domain's step state
 template <typename T, bool FORCED>
-__global__ __launch_bounds__(256) void k_sweep(DevDomain d) {
+__global__ __launch_bounds__(256) void k_sweep(DevDomain d, int gx, int gy, int chunk) {
   using C = typename Store<T>::C;
   if (!step_live(d.ctl)) return;
+  const int t = chunk ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int bx = t % gx, r = t / gx, by = r % gy, z = r / gy;
+  if (z >= d.nz) return;
   const int cur = d.ctl->cur;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int y = by * blockDim.y + threadIdx.y;
   if (x >= d.nx || y >= d.ny) return;
   // (selects, not an index: a run-time index into the by-value argument would
   // place the whole descriptor in scratch memory)
   const T* src = (const T*)(cur ? d.pdf[1] : d.pdf[0]);
   T* dst = (T*)(cur ? d.pdf[0] : d.pdf[1]);
-  sweep_cell<T, FORCED>(d, src, dst, x, y, blockIdx.z, (C)d.s_plus, (C)d.s_minus,
+  sweep_cell<T, FORCED>(d, src, dst, x, y, z, (C)d.s_plus, (C)d.s_minus,
                         (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
 }
 
@@ -315,13 +321,18 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
     block.y = 256 / block.x;
   }
   block.z = 1;
-  grid.x = (d.nx + block.x - 1) / block.x;
-  grid.y = (d.ny + block.y - 1) / block.y;
-  grid.z = d.nz;
+  const int gx = (d.nx + block.x - 1) / block.x, gy = (d.ny + block.y - 1) / block.y;
+  // Tile order, measured: with whole rows per tile, contiguous runs of tiles
+  // per XCD (122.5 against 125.6 us at 128x128x256); with rows split into
+  // pieces, plain order (1.56 against 1.63 ms at 384^3, 2.06 against 2.16 ms
+  // at 512^3)
+  const int chunk = gx == 1 ? 1 : 0;
+  const int tiles = gx * gy * d.nz;
+  grid = dim3(chunk ? xcd_grid(tiles) : tiles);
   if (d.forced)
-    hipLaunchKernelGGL((k_sweep<T, true>), grid, block, 0, s, d);
+    hipLaunchKernelGGL((k_sweep<T, true>), grid, block, 0, s, d, gx, gy, chunk);
   else
-    hipLaunchKernelGGL((k_sweep<T, false>), grid, block, 0, s, d);
+    hipLaunchKernelGGL((k_sweep<T, false>), grid, block, 0, s, d, gx, gy, chunk);
 }
 
 void launch_sweep(const DevDomain& d, hipStream_t s) {
