@@ -45,7 +45,7 @@ int list_cap(const lbmdem_config& c) {
 
 bool ball_possible(const lbmdem_config& c) {
   const int he = stage_edge(c);
-  const size_t lds = (((size_t)he * he * he + 15) & ~(size_t)15) + 2 * (size_t)list_cap(c);
+  const size_t lds = ball_lds_bytes(he, list_cap(c));
   if (lds > BALL_LDS_MAX || (size_t)he * he * he > 65535) return false;
   const int n[3] = {c.nx, c.ny, c.nz};
   for (int a = 0; a < 3; ++a)

@@ -196,6 +196,15 @@ constexpr int XCDS = 8;
 __device__ __forceinline__ int xcd_tile(int w, int G) { return (w & (XCDS - 1)) * (G / XCDS) + w / XCDS; }
 inline int xcd_grid(int tiles) { return (tiles + XCDS - 1) / XCDS * XCDS; }
 
+// LDS of a k_commit_ball block: the staged cube of cell codes (he^3 bytes),
+// the surface-cell list (16-bit cube indices) and one chunk's link list (up
+// to 18 links for each of BALL_THREADS cells, 32 bits each)
+constexpr int BALL_THREADS = 256;
+inline size_t ball_lds_bytes(int he, int list_cap) {
+  return (((size_t)he * he * he + 15) & ~(size_t)15) + ((2 * (size_t)list_cap + 15) & ~(size_t)15) +
+         4 * (size_t)(Q - 1) * BALL_THREADS;
+}
+
 // domain of block b: the k with start[k] <= b < start[k+1] (binary search)
 __device__ __forceinline__ int batch_domain(const int* start, int ndom, int b) {
   int lo = 0, hi = ndom - 1;

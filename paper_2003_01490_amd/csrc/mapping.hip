@@ -774,6 +774,104 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step, int ad
 // surface list.
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
+// A link of the ball pass, packed: cube index t of the solid cell y (bits
+// 0-15), q (16-20), qbar (21-25) and c_q + 1 per axis (26-31).
+__device__ __forceinline__ uint32_t link_entry(int t, int q) {
+  return (uint32_t)t | ((uint32_t)q << 16) | ((uint32_t)OPP[q] << 21) | ((uint32_t)(CX[q] + 1) << 26) |
+         ((uint32_t)(CY[q] + 1) << 28) | ((uint32_t)(CZ[q] + 1) << 30);
+}
+
+constexpr int BALL_LINK_UNROLL = 2;
+
+// Links k0, k0 + blockDim.x, ... (at most U of them below tot) of sphere i,
+// all loads issued before any is used.  y - c_q fluid: boundary value of
+// Eq. (MEM_CLI) into slot qbar of y (delta = 1/2 in the coefficients where
+// y - 2 c_q is not fluid), force of Eq. (MEM_Fq) and its torque about the
+// centre; y - c_q a wall or another sphere's solid: the missing-link force
+// 2 w_q c_q with the arm to the mid-point of the link.
+template <typename T, int U>
+__device__ __forceinline__ void ball_links(const DevDomain& d, T* buf, size_t N, const uint8_t* st,
+                                           const uint32_t* lk, int k0, int tot, int he, const int* lo,
+                                           const double* xp, const double* up, const double* wp, double R,
+                                           double* acc) {
+  bool ok[U], cli[U];
+  int code[U], q[U], qb[U], cq[U][3], y[U][3], xg[U], xmg[U];
+  T gq[U], gqb[U], gm[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * (int)blockDim.x;
+    ok[u] = k < tot;
+    const uint32_t e = ok[u] ? lk[k] : 0u;
+    const int t = (int)(e & 0xFFFFu);
+    q[u] = (int)((e >> 16) & 31u);
+    qb[u] = (int)((e >> 21) & 31u);
+    cq[u][0] = (int)((e >> 26) & 3u) - 1;
+    cq[u][1] = (int)((e >> 28) & 3u) - 1;
+    cq[u][2] = (int)((e >> 30) & 3u) - 1;
+    const int h[3] = {t % he, (t / he) % he, t / (he * he)};
+    y[u][0] = d.walls[0] ? lo[0] + h[0] : wrapmod(lo[0] + h[0], d.nx);
+    y[u][1] = d.walls[1] ? lo[1] + h[1] : wrapmod(lo[1] + h[1], d.ny);
+    y[u][2] = d.walls[2] ? lo[2] + h[2] : wrapmod(lo[2] + h[2], d.nz);
+    const int off = cq[u][0] + he * (cq[u][1] + he * cq[u][2]);
+    code[u] = ok[u] ? (int)st[t - off] : L_OWN;
+    cli[u] = false;
+    xg[u] = xmg[u] = 0;
+    gq[u] = gqb[u] = gm[u] = (T)0.0f;
+    if (code[u] <= L_SHELL) {
+      // wall layers shield every non-wall cell, so y - c_q stays in range
+      const int xi = wrapi(y[u][0] - cq[u][0], d.nx), xj = wrapi(y[u][1] - cq[u][1], d.ny),
+                xk = wrapi(y[u][2] - cq[u][2], d.nz);
+      xg[u] = (int)cidx(d, xi, xj, xk);
+      if (d.boundary == 0 && st[t - 2 * off] <= L_SHELL) {
+        cli[u] = true;
+        xmg[u] = (int)cidx(d, wrapi(xi - cq[u][0], d.nx), wrapi(xj - cq[u][1], d.ny), wrapi(xk - cq[u][2], d.nz));
+      }
+      gq[u] = buf[(size_t)q[u] * N + xg[u]];
+      gqb[u] = buf[(size_t)qb[u] * N + xg[u]];
+      if (cli[u]) gm[u] = buf[(size_t)q[u] * N + xmg[u]];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (!ok[u]) continue;
+    const int* c = cq[u];
+    const double wq = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] == 1 ? 1.0 / 18 : 1.0 / 36;
+    double Fq[3], arm[3];
+    if (code[u] <= L_SHELL) {
+      const int xi = wrapi(y[u][0] - c[0], d.nx), xj = wrapi(y[u][1] - c[1], d.ny), xk = wrapi(y[u][2] - c[2], d.nz);
+      double r[3];
+      r[0] = min_image(((double)xi + 0.5) - xp[0], d.nx, d.walls[0]);
+      r[1] = min_image(((double)xj + 0.5) - xp[1], d.ny, d.walls[1]);
+      r[2] = min_image(((double)xk + 0.5) - xp[2], d.nz, d.walls[2]);
+      const double dl = link_delta(r, c, R);
+      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * c[a];
+      double ub[3];
+      ub[0] = up[0] + (wp[1] * arm[2] - wp[2] * arm[1]);
+      ub[1] = up[1] + (wp[2] * arm[0] - wp[0] * arm[2]);
+      ub[2] = up[2] + (wp[0] * arm[1] - wp[1] * arm[0]);
+      const double dd = cli[u] ? dl : 0.5;
+      const double vq = raw_to_d<T>(gq[u]);
+      double val = vq;
+      if (cli[u]) val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (raw_to_d<T>(gm[u]) - raw_to_d<T>(gqb[u]));
+      val -= 4.0 / (1.0 + 2.0 * dd) * wq * 3.0 * (ub[0] * c[0] + ub[1] * c[1] + ub[2] * c[2]);
+      stv<T>(buf + (size_t)qb[u] * N + cidx(d, y[u][0], y[u][1], y[u][2]), val);
+      const double fq = vq + wq, fb = val + wq;
+      for (int a = 0; a < 3; ++a) Fq[a] = (c[a] - ub[a]) * fq - (-c[a] - ub[a]) * fb;
+    } else {
+      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * wq * c[a];
+      arm[0] = min_image(((double)y[u][0] + 0.5) - xp[0], d.nx, d.walls[0]) - 0.5 * c[0];
+      arm[1] = min_image(((double)y[u][1] + 0.5) - xp[1], d.ny, d.walls[1]) - 0.5 * c[1];
+      arm[2] = min_image(((double)y[u][2] + 0.5) - xp[2], d.nz, d.walls[2]) - 0.5 * c[2];
+    }
+    acc[0] += Fq[0];
+    acc[1] += Fq[1];
+    acc[2] += Fq[2];
+    acc[3] += arm[1] * Fq[2] - arm[2] * Fq[1];
+    acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
+    acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int i) {
   const int cur = map_buffer(d.ctl, in_step);
@@ -785,6 +883,7 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   const int NS = he * he * he;
   uint8_t* st = smem;
   uint16_t* list = reinterpret_cast<uint16_t*>(smem + ((NS + 15) & ~15));
+  uint32_t* lk = reinterpret_cast<uint32_t*>(smem + ((NS + 15) & ~15) + ((2 * d.list_cap + 15) & ~15));
   __shared__ double red[6][4];
   const double xp[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
   const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
@@ -920,20 +1019,42 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     __syncthreads();
   }
 
-  // 4. links of the listed cells
+  // 4. links: the listed cells in chunks of one cell per thread; a chunk's
+  // links (y, q) with y - c_q not this sphere's solid are listed in cell and
+  // direction order (ordered compaction), then shared out over all threads
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int nl = base;  // the same in every thread
-  for (int e = threadIdx.x; e < nl; e += blockDim.x) {
-    const int t = list[e];
-    const int hx = t % he, hy = (t / he) % he, hz = t / (he * he);
-    const int ii = d.walls[0] ? lo[0] + hx : wrapmod(lo[0] + hx, n[0]);
-    const int jj = d.walls[1] ? lo[1] + hy : wrapmod(lo[1] + hy, n[1]);
-    const int kk = d.walls[2] ? lo[2] + hz : wrapmod(lo[2] + hz, n[2]);
-    const long long yc = cidx(d, ii, jj, kk);
-    const LinkCtx<T> lc{d, buf, N, st, true, t, he, he, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
-    link_batch<T, 1>(lc, acc);
-    link_batch<T, 7>(lc, acc);
-    link_batch<T, 13>(lc, acc);
+  __shared__ int wsum[4];
+  for (int c0 = 0; c0 < nl; c0 += blockDim.x) {
+    const int e = c0 + threadIdx.x;
+    uint32_t mask = 0u;
+    int t = 0;
+    if (e < nl) {
+      t = list[e];
+#pragma unroll
+      for (int q = 1; q < Q; ++q)
+        if (st[t - CX[q] - he * (CY[q] + he * CZ[q])] != L_OWN) mask |= 1u << q;
+    }
+    const int cnt = __popc(mask);
+    int v = cnt;  // inclusive scan over the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+      const int w = __shfl_up(v, o, 64);
+      if (lane >= o) v += w;
+    }
+    if (lane == 63) wsum[wid] = v;
+    __syncthreads();
+    int off = v - cnt, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wid) off += wsum[w];
+      tot += wsum[w];
+    }
+#pragma unroll
+    for (int q = 1; q < Q; ++q)
+      if (mask & (1u << q)) lk[off++] = link_entry(t, q);
+    __syncthreads();
+    for (int k0 = threadIdx.x; k0 < tot; k0 += BALL_LINK_UNROLL * blockDim.x)
+      ball_links<T, BALL_LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
+    __syncthreads();  // the next chunk reuses the list and the wave sums
   }
   // 5. fixed-order block reduction
   for (int k = 0; k < 6; ++k) {
@@ -955,7 +1076,7 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
 // four waves per SIMD (at most 128 VGPRs; measured 7 % faster at 10,000
 // spheres than the three that the unconstrained allocation allows)
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_commit_ball(DevDomain d,
+__global__ __launch_bounds__(BALL_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_commit_ball(DevDomain d,
                                                                                              int in_step,
                                                                                              int advance) {
   const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -983,9 +1104,8 @@ static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, i
   const int blocks = d.map_ball ? xcd_grid(d.P) : nsb * d.RB;
   const int fold = advance && blocks <= FOLD_ADVANCE_MAX_BLOCKS;
   if (d.map_ball) {
-    const size_t lds = (((size_t)d.stage_edge * d.stage_edge * d.stage_edge + 15) & ~(size_t)15) +
-                       2 * (size_t)d.list_cap;
-    hipLaunchKernelGGL(k_commit_ball<T>, dim3(blocks), dim3(256), lds, s, d, in_step, fold);
+    hipLaunchKernelGGL(k_commit_ball<T>, dim3(blocks), dim3(BALL_THREADS), ball_lds_bytes(d.stage_edge, d.list_cap), s, d,
+                       in_step, fold);
   } else {
     hipLaunchKernelGGL(k_commit<T>, dim3(blocks), dim3(256), 0, s, d, in_step, fold);
   }
