@@ -434,100 +434,14 @@ struct LinkCtx {
   double R;
 };
 
-// Six directions Q0..Q0+5 of a solid cell y of sphere i: classify the cell
-// x = y - c_q (fluid link, missing link or own solid), issue all PDF loads of
-// the batch, then form the boundary values of Eq. (MEM_CLI) (stored into slot
-// qbar of y), the momentum-exchange forces of Eq. (MEM_Fq) and their torques.
-template <typename T, int Q0>
-__device__ inline void link_batch(const LinkCtx<T>& c, double* acc) {
-  constexpr int NB = 6;
-  const DevDomain& d = c.d;
-  int code[NB];
-  int xg[NB], xmg[NB];  // cell indices (lattices have fewer than 2^31 cells)
-  bool cli[NB];
-  T gq[NB], gqb[NB], gm[NB];  // raw stored values, widened where used
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int q = Q0 + k;
-    const int cq0 = CX[q], cq1 = CY[q], cq2 = CZ[q];
-    // wall layers shield every non-wall cell, so y - c_q stays in range
-    const int xi = wrapi(c.ii - cq0, d.nx), xj = wrapi(c.jj - cq1, d.ny), xk = wrapi(c.kk - cq2, d.nz);
-    xg[k] = (int)cidx(d, xi, xj, xk);
-    if (c.staged) {
-      code[k] = c.st[c.cidx0 - cq0 - c.HX * (cq1 + c.HY * cq2)];
-    } else {
-      int zo = -1;
-      const int zs = new_state(d, xg[k], c.stamp, &zo);
-      code[k] = zs == S_WALL ? L_WALL : (zs == S_SOLID ? (zo == c.i ? L_OWN : L_OTHER) : (zs == S_SHELL ? L_SHELL : L_FLUID));
-    }
-    cli[k] = false;
-    xmg[k] = 0;
-    gq[k] = gqb[k] = gm[k] = (T)0.0f;
-    if (code[k] <= L_SHELL) {
-      if (d.boundary == 0) {
-        xmg[k] = (int)cidx(d, wrapi(xi - cq0, d.nx), wrapi(xj - cq1, d.ny), wrapi(xk - cq2, d.nz));
-        if (c.staged) {
-          cli[k] = c.st[c.cidx0 - 2 * cq0 - c.HX * (2 * cq1 + c.HY * 2 * cq2)] <= L_SHELL;
-        } else {
-          int mo;
-          cli[k] = is_fluid_state(new_state(d, xmg[k], c.stamp, &mo));
-        }
-      }
-      gq[k] = c.buf[(size_t)q * c.N + xg[k]];
-      gqb[k] = c.buf[(size_t)OPP[q] * c.N + xg[k]];
-      if (cli[k]) gm[k] = c.buf[(size_t)q * c.N + xmg[k]];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int q = Q0 + k;
-    if (code[k] == L_OWN) continue;
-    const int cq[3] = {CX[q], CY[q], CZ[q]};
-    double Fq[3], arm[3];
-    if (code[k] <= L_SHELL) {
-      const int xi = wrapi(c.ii - cq[0], d.nx), xj = wrapi(c.jj - cq[1], d.ny), xk = wrapi(c.kk - cq[2], d.nz);
-      double r[3];
-      r[0] = min_image(((double)xi + 0.5) - c.xp[0], d.nx, d.walls[0]);
-      r[1] = min_image(((double)xj + 0.5) - c.xp[1], d.ny, d.walls[1]);
-      r[2] = min_image(((double)xk + 0.5) - c.xp[2], d.nz, d.walls[2]);
-      const double dl = link_delta(r, cq, c.R);
-      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * cq[a];
-      double ub[3];
-      ub[0] = c.up[0] + (c.wp[1] * arm[2] - c.wp[2] * arm[1]);
-      ub[1] = c.up[1] + (c.wp[2] * arm[0] - c.wp[0] * arm[2]);
-      ub[2] = c.up[2] + (c.wp[0] * arm[1] - c.wp[1] * arm[0]);
-      const double dd = cli[k] ? dl : 0.5;
-      const double vq = raw_to_d<T>(gq[k]);
-      double val = vq;
-      if (cli[k]) val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (raw_to_d<T>(gm[k]) - raw_to_d<T>(gqb[k]));
-      val -= 4.0 / (1.0 + 2.0 * dd) * WQ[q] * 3.0 * (ub[0] * cq[0] + ub[1] * cq[1] + ub[2] * cq[2]);
-      stv<T>(c.buf + (size_t)OPP[q] * c.N + c.yc, val);
-      const double fq = vq + WQ[q], fb = val + WQ[q];
-      for (int a = 0; a < 3; ++a) Fq[a] = (cq[a] - ub[a]) * fq - (-cq[a] - ub[a]) * fb;
-    } else {
-      // wall or another sphere's solid: missing link, F_q = 2 w_q c_q
-      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * WQ[q] * cq[a];
-      arm[0] = min_image(((double)c.ii + 0.5) - c.xp[0], d.nx, d.walls[0]) - 0.5 * cq[0];
-      arm[1] = min_image(((double)c.jj + 0.5) - c.xp[1], d.ny, d.walls[1]) - 0.5 * cq[1];
-      arm[2] = min_image(((double)c.kk + 0.5) - c.xp[2], d.nz, d.walls[2]) - 0.5 * cq[2];
-    }
-    acc[0] += Fq[0];
-    acc[1] += Fq[1];
-    acc[2] += Fq[2];
-    acc[3] += arm[1] * Fq[2] - arm[2] * Fq[1];
-    acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
-    acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
-  }
-}
-
-
 // All 18 directions of a solid cell y of sphere i at once, for the few-sphere
 // boundary pass, which is bound by memory latency rather than traffic: the
 // PDF loads of every direction are issued unconditionally (a neighbour's own
 // slots stand in where a direction needs no value) before any is used, and
 // the boundary values are stored after all of them are formed, so the cell
-// costs one memory round trip instead of one per batch.  Arithmetic as in
-// link_batch.
+// costs one memory round trip.  Boundary values of Eq. (MEM_CLI) go into
+// slot qbar of y; forces of Eq. (MEM_Fq) and the missing-link forces, with
+// their torques, are summed per link in the same arithmetic as ball_links.
 template <typename T>
 __device__ inline void link_all(const LinkCtx<T>& c, double* acc) {
   const DevDomain& d = c.d;
