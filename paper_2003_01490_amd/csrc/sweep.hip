@@ -2,9 +2,10 @@
 // with the rates of Eqs. TRTmatrix / TRTbulkmatrix, adaptive shell of Sec. 2.3.2).
 //
 // One thread per cell, one block per whole x-row group where rows are at most
-// 256 cells, so that the +-1 x-shifted loads of a row stay inside the block
-// and every source value is fetched from HBM once (wider rows are split into
-// pieces; the x-shifted loads then fetch one shared line per piece twice).  The PDF slots of solid cells carry the boundary
+// 256 cells (512 at FP16), so that the +-1 x-shifted loads of a row stay
+// inside the block and every source value is fetched from HBM once (wider
+// rows are split into pieces; the x-shifted loads then fetch one shared line
+// per piece twice).  The PDF slots of solid cells carry the boundary
 // values of the particle links that stream out of them (written by the
 // boundary kernel), so a fluid cell pulls 19 values without branching.  Wall
 // layers are fixed, so the sweep knows from the cell's coordinates which
@@ -260,8 +261,10 @@ __device__ __forceinline__ void sweep_cell(const DevDomain& d, const T* __restri
 // launch_sweep_t), gx x gy tiles per z plane, x fastest; with `chunk` each
 // XCD takes a contiguous run of tiles; the current buffer is read from the
 // domain's step state
+constexpr int SWEEP_MAX_THREADS = 512;
+
 template <typename T, bool FORCED>
-__global__ __launch_bounds__(256) void k_sweep(DevDomain d, int gx, int gy, int chunk) {
+__global__ __launch_bounds__(SWEEP_MAX_THREADS) void k_sweep(DevDomain d, int gx, int gy, int chunk) {
   using C = typename Store<T>::C;
   if (!step_live(d.ctl)) return;
   const int t = chunk ? xcd_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -305,10 +308,12 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const DevDomain* __restrict
 template <typename T>
 static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
   dim3 block, grid;
-  if (d.nx <= 256) {
-    // whole rows per block: the periodic x-wrap stays inside the block
+  if (d.nx <= 256 || (d.nx <= SWEEP_MAX_THREADS && d.nx * sizeof(T) <= 1024)) {
+    // whole rows per block: the periodic x-wrap stays inside the block (a
+    // 512-wide FP16 row in one block: 1.92 against 2.06 ms in 128 x 2 pieces
+    // at 512^3; 384- and 512-wide FP32 rows were slower whole)
     block.x = d.nx;
-    block.y = 256 / d.nx;
+    block.y = d.nx <= 256 ? 256 / d.nx : 1;
   } else {
     // 128 x 2 measured best for 384-wide rows
     const int cand[4] = {128, 256, 192, 64};
@@ -322,11 +327,10 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
   }
   block.z = 1;
   const int gx = (d.nx + block.x - 1) / block.x, gy = (d.ny + block.y - 1) / block.y;
-  // Tile order, measured: with whole rows per tile, contiguous runs of tiles
-  // per XCD (122.5 against 125.6 us at 128x128x256); with rows split into
-  // pieces, plain order (1.56 against 1.63 ms at 384^3, 2.06 against 2.16 ms
-  // at 512^3)
-  const int chunk = gx == 1 ? 1 : 0;
+  // Tile order, measured: rows of up to 256 cells, contiguous runs of tiles
+  // per XCD (122.5 against 125.6 us at 128x128x256); wider rows, plain order
+  // (1.56 against 1.63 ms at 384^3 FP32, 1.92 against 1.98 ms at 512^3 FP16)
+  const int chunk = d.nx <= 256 ? 1 : 0;
   const int tiles = gx * gy * d.nz;
   grid = dim3(chunk ? xcd_grid(tiles) : tiles);
   if (d.forced)

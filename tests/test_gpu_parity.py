@@ -64,6 +64,39 @@ def test_fluid_only_periodic_random_pdf(coll):
     _compare_fields(g, o)
 
 
+@pytest.mark.parametrize("storage", [0, 2])
+def test_wide_rows(storage):
+    """Rows wider than 256 cells: 320-wide FP64 rows are swept in 64-cell
+    pieces (parity at 1e-12 against the oracle); 320-wide FP16 rows in one
+    block each (against the oracle within a bound of the FP16 storage
+    rounding: 2^-11 relative per stored deviation, accumulated over the 12
+    steps, on deviations of at most ~0.05).  z walls moving in x on both
+    sides, so the wall branch runs in wide rows too."""
+    n = (320, 5, 7)
+    _case(f"wide rows {n} storage {storage}")
+    wl = W.Workload("wide", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.02,
+                                          max_spheres=1, wall_u_lo=(0.01, 0.0, 0.0), wall_u_hi=(-0.02, 0.0, 0.0)),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    f = random_pdf(n, seed=31, u0=(0.02, -0.01, 0.0))
+    o = oracle_domain(wl)
+    g = gpu_domain(wl, storage=storage)
+    o.set_pdf(f)
+    g.set_pdf(f)
+    o.step(12)
+    g.step(12)
+    if storage == 0:
+        _compare_fields(g, o)
+        return
+    fo, fg = o.field("pdf"), g.field("pdf")
+    code = o.flags()[0]
+    fl = code <= O.SHELL
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None, None, None]
+    dev = np.abs(fo - w)[:, fl].max()
+    err = np.abs(fg - fo)[:, fl].max()
+    print(f"  FP16 wide rows: max |df| {err:.2e}, max |f - w| {dev:.2e}", flush=True)
+    assert err <= 12 * 2.0 ** -11 * dev, (err, dev)
+
+
 @pytest.mark.parametrize("coll", [O.TRT_AB, O.TRT_B, O.SRT])
 def test_body_force_fluid_and_fixed_sphere(coll):
     """Guo forcing (the oracle's moment-space form against the sweep's
