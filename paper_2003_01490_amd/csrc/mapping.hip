@@ -79,6 +79,34 @@ __device__ inline void sphere_box(const DevDomain& d, int i, bool with_old, Box&
   }
 }
 
+// cells whose centre can lie within R of the mapped centre of sphere i
+// (the cells a mapping update can uncover)
+__device__ inline void mapped_ball_box(const DevDomain& d, int i, Box& b) {
+  const double R = d.p.R[i];
+  const int n[3] = {d.nx, d.ny, d.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double co = d.p.xmap[3 * i + a];
+    if (!isfinite(co)) {
+      for (int e = 0; e < 3; ++e) b.lo[e] = b.ext[e] = 0;
+      return;
+    }
+    int lo = (int)floor(co - R) - 1;
+    int hi = (int)floor(co + R) + 1;
+    if (d.walls[a]) {
+      lo = max(lo, 0);
+      hi = min(hi, n[a] - 1);
+    }
+    int e = hi - lo + 1;
+    if (!d.walls[a] && e >= n[a]) {
+      lo = 0;
+      e = n[a];
+    }
+    b.lo[a] = lo;
+    b.ext[a] = max(e, 0);
+  }
+}
+
 __device__ inline double cell_d2(const DevDomain& d, int i, int j, int k, const double* xp) {
 #pragma clang fp contract(off)
   const double dx = min_image(((double)i + 0.5) - xp[0], d.nx, d.walls[0]);
@@ -355,7 +383,7 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
   if (threadIdx.x == 0) ncand = 0;
   __syncthreads();
   Box bx;
-  sphere_box(d, i, true, bx);
+  mapped_ball_box(d, i, bx);
   T* buf = (T*)d.pdf[cur];
   const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
   const double xn[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
