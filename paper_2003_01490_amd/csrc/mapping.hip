@@ -921,45 +921,55 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     const long long c = cidx(d, ijk[0], ijk[1], ijk[2]);
     const uint8_t sc = in ? st[h[0] + he * (h[1] + he * h[2])] : L_UNSET;
     if (sc == L_WALL || sc == L_OTHER) continue;
+    uint8_t nf;
+    int no = -1;
     if (sc == L_OWN) {
-      d.flags[c] = F_SOLID;
-      d.owner[c] = i;
+      nf = F_SOLID;
+      no = i;
     } else if (sc == L_SHELL || sc == L_FLUID) {
-      d.flags[c] = sc == L_SHELL ? F_SHELL : (uint8_t)0;
+      nf = sc == L_SHELL ? F_SHELL : (uint8_t)0;
     } else {
-      int own = -1;
-      const int ns = new_state(d, c, stamp, &own);
+      const int ns = new_state(d, c, stamp, &no);
       if (ns == S_WALL) continue;
-      d.flags[c] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
-      if (ns == S_SOLID) d.owner[c] = own;
+      nf = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
+      if (ns != S_SOLID) no = -1;
     }
+    // (storing only where the state changes was measured slower)
+    d.flags[c] = nf;
+    if (no >= 0) d.owner[c] = no;
   }
 
   // 3. solid cells of this sphere with a neighbour that is not, listed in
   // cube order (ordered compaction: wavefront ballots and per-wave offsets),
-  // so that every cell is summed by the same thread on every run
-  __shared__ int wcount[4];
+  // so that every cell is summed by the same thread on every run.  Only the
+  // central box of edge 2 ceil(R) + 3 can hold cells of this sphere (their
+  // centres lie within R of x_p); its x-fastest order is the cube's.  The
+  // wave counts alternate between two slots, so one barrier per pass does.
+  __shared__ int wcount[2][4];
   int base = 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int t0 = 0; t0 < NS; t0 += blockDim.x) {
-    const int t = t0 + threadIdx.x;
+  const int rc = (int)ceil(R) + 1, E = 2 * rc + 1, h0 = H - rc;
+  const int NE = finite ? E * E * E : 0;
+  for (int t0 = 0, pass = 0; t0 < NE; t0 += blockDim.x, pass ^= 1) {
+    const int u = t0 + threadIdx.x;
+    const int t = h0 + u % E + he * (h0 + (u / E) % E + he * (h0 + u / (E * E)));
     bool surf = false;
-    if (t < NS && st[t] == L_OWN) {
+    if (u < NE && st[t] == L_OWN) {
 #pragma unroll
       for (int q = 1; q < Q; ++q) surf = surf || st[t + CX[q] + he * (CY[q] + he * CZ[q])] != L_OWN;
     }
     const unsigned long long m = __ballot(surf);
-    if (lane == 0) wcount[wid] = __popcll(m);
+    if (lane == 0) wcount[pass][wid] = __popcll(m);
     __syncthreads();
     int off = base, tot = 0;
     for (int w = 0; w < nw; ++w) {
-      if (w < wid) off += wcount[w];
-      tot += wcount[w];
+      if (w < wid) off += wcount[pass][w];
+      tot += wcount[pass][w];
     }
     if (surf) list[off + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)t;
     base += tot;
-    __syncthreads();
   }
+  __syncthreads();
 
   // 4. links: the listed cells in chunks of one cell per thread; a chunk's
   // links (y, q) with y - c_q not this sphere's solid are listed in cell and
