@@ -69,7 +69,7 @@ def traffic_record(workload: str, storage: str):
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "pmc_traffic_*.md"))):
         for block in re.findall(r"```json\n(.*?)\n```", open(f).read(), re.S):
             rec = json.loads(block)
-            if rec.get("sweep_src_sha256") == sha and rec.get("workload", "").startswith(workload) \
+            if rec.get("sweep_src_sha256") == sha and rec.get("workload", "").split(" ")[0] == workload \
                     and rec["workload"].endswith(tag):
                 return rec["bytes_per_launch"], os.path.relpath(f, ROOT)
     return None, None
@@ -324,7 +324,7 @@ def main():
     bytes_per_launch = dom.sweep_bytes()
     achieved = bytes_per_launch / sweep_avg_s / 1e9
     s0 = dom.sphere(0)
-    traffic, traffic_src = traffic_record(wl.name, args.storage)
+    traffic, traffic_src = traffic_record(args.workload, args.storage)
 
     result = {
         "metric": METRIC,
