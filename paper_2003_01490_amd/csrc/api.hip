@@ -699,9 +699,21 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   for (int k = 0; k < nsteps; ++k) {
     hipError_t e = hipSuccess;
     hipStream_t ds = s;
+    // With the sweep timed, the event that opens its timing also releases the
+    // second stream (each recorded event costs the queue a few microseconds).
+    lbmdem_domain::Ev sw{nullptr, nullptr, 0};
+    if (ov && dom->prof >= 1) {
+      if (dom->pending.size() > 4096) {
+        HIPCHK(dom, hipStreamSynchronize(s));
+        harvest(dom);
+      }
+      sw = {get_event(dom), get_event(dom), 0};
+      if (!sw.a || !sw.b) return fail(dom, LBMDEM_EDEVICE, "event creation failed");
+    }
     if (ov) {
-      HIPCHK(dom, hipEventRecord(dom->ev_fork, s));
-      HIPCHK(dom, hipStreamWaitEvent(dom->side, dom->ev_fork, 0));
+      hipEvent_t fork = sw.a ? sw.a : dom->ev_fork;
+      HIPCHK(dom, hipEventRecord(fork, s));
+      HIPCHK(dom, hipStreamWaitEvent(dom->side, fork, 0));
       ds = dom->side;
     }
     auto dem = [&] {
@@ -715,7 +727,13 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
       dem();
     } else {
       dem();
-      timed(dom, 0, s, [&] { launch_sweep(dom->d, s); });
+      if (sw.a) {
+        launch_sweep(dom->d, s);
+        HIPCHK(dom, hipEventRecord(sw.b, s));
+        dom->pending.push_back(sw);
+      } else {
+        launch_sweep(dom->d, s);
+      }
       HIPCHK(dom, hipEventRecord(dom->ev_join, ds));
       HIPCHK(dom, hipStreamWaitEvent(s, dom->ev_join, 0));
     }
