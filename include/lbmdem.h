@@ -95,7 +95,7 @@ typedef struct lbmdem_config {
   double cut_n, cut_tt, cut_tr; /* lubrication cut-offs; paper: 2/3, 1/2, 1/2   */
   int32_t lub_mask;         /* bit0 normal, bit1 tangential translation, bit2 rotation */
   int32_t max_spheres;      /* capacity, sizes the device region                 */
-  double max_radius;        /* largest sphere radius that will be added          */
+  double max_radius;        /* largest sphere radius that will be added, <= 1000 */
   int32_t dem_kernel;       /* DEM sub-cycle kernel: 0 automatic (one workgroup up
                                to 256 spheres, else one thread per sphere), 1 one
                                workgroup (all-pairs neighbour search), 2 one

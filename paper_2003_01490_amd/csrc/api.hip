@@ -171,6 +171,8 @@ const char* check_config(const lbmdem_config* c) {
   if (c->n_sub < 1) return "n_sub must be >= 1";
   if (c->max_spheres < 0) return "max_spheres must be >= 0";
   if (c->max_spheres > 0 && !(c->max_radius > 0.0)) return "max_radius must be positive";
+  // the boundary passes index a block's cells with 16 bits
+  if (c->max_spheres > 0 && !(c->max_radius <= 1000.0)) return "max_radius must be at most 1000";
   if (!(c->e_dry > 0.0 && c->e_dry <= 1.0)) return "e_dry must lie in (0, 1]";
   if (!(c->poisson_ratio >= 0.0 && c->poisson_ratio < 1.0)) return "poisson_ratio must lie in [0, 1)";
   if (!(c->friction >= 0.0)) return "friction must be non-negative";

@@ -444,99 +444,108 @@ __device__ __forceinline__ double raw_to_d<float>(float v) { return (double)v; }
 template <>
 __device__ __forceinline__ double raw_to_d<__half>(__half v) { return (double)__half2float(v); }
 
-template <typename T>
-struct LinkCtx {
-  const DevDomain& d;
-  T* buf;
-  size_t N;
-  const uint8_t* st;
-  bool staged;
-  int cidx0, HX, HY;
-  int ii, jj, kk;
-  long long yc;
-  int i;
-  uint32_t stamp;
-  const double* xp;
-  const double* up;
-  const double* wp;
-  double R;
-};
+// A link of the boundary passes, packed: index t of the solid cell y in the
+// block's cell set (bits 0-15), q (16-20), qbar (21-25) and c_q + 1 per axis
+// (26-31).
+__device__ __forceinline__ uint32_t link_entry(int t, int q) {
+  return (uint32_t)t | ((uint32_t)q << 16) | ((uint32_t)OPP[q] << 21) | ((uint32_t)(CX[q] + 1) << 26) |
+         ((uint32_t)(CY[q] + 1) << 28) | ((uint32_t)(CZ[q] + 1) << 30);
+}
 
-// All 18 directions of a solid cell y of sphere i at once, for the few-sphere
-// boundary pass, which is bound by memory latency rather than traffic: the
-// PDF loads of every direction are issued unconditionally (a neighbour's own
-// slots stand in where a direction needs no value) before any is used, and
-// the boundary values are stored after all of them are formed, so the cell
-// costs one memory round trip.  Boundary values of Eq. (MEM_CLI) go into
-// slot qbar of y; forces of Eq. (MEM_Fq) and the missing-link forces, with
-// their torques, are summed per link in the same arithmetic as ball_links.
-template <typename T>
-__device__ inline void link_all(const LinkCtx<T>& c, double* acc) {
-  const DevDomain& d = c.d;
-  int code[Q];
-  bool cli[Q];
-  T vq[Q], vqb[Q], vm[Q];
+constexpr int LINK_UNROLL = 2;
+
+// State code of the cell z = y - m c_q seen from sphere i: from the staged
+// slab (index cidx0 of y, staged row pitch HX, HY) or from the global arrays.
+__device__ __forceinline__ int slab_code(const DevDomain& d, const uint8_t* st, bool stg, int cidx0, int HX,
+                                         int HY, const int* c, int m, long long zg, uint32_t stamp, int i) {
+  if (stg) return st[cidx0 - m * (c[0] + HX * (c[1] + HY * c[2]))];
+  int zo = -1;
+  const int zs = new_state(d, zg, stamp, &zo);
+  return zs == S_WALL ? L_WALL : (zs == S_SOLID ? (zo == i ? L_OWN : L_OTHER) : (zs == S_SHELL ? L_SHELL : L_FLUID));
+}
+
+// Links k0, k0 + blockDim.x, ... (at most U below tot) of one row chunk of
+// a slab block, all loads issued before any is used: the cell is entry bits
+// 0-15 = tx + EX ty of the chunk (plane kk, rows from jy0, columns from ix0).
+// y - c_q fluid: boundary value of Eq. (MEM_CLI) into slot qbar of y (delta =
+// 1/2 in the coefficients where y - 2 c_q is not fluid), force of Eq.
+// (MEM_Fq) and its torque; y - c_q a wall or another sphere's solid: the
+// missing-link force 2 w_q c_q with the arm to the mid-point of the link.
+// The same arithmetic as ball_links.
+template <typename T, int U>
+__device__ __forceinline__ void slab_links(const DevDomain& d, T* buf, size_t N, const uint8_t* st, bool stg,
+                                           const uint32_t* lk, int k0, int tot, int EX, int HX, int HY, int ix0,
+                                           int jy0, int kk, int i, uint32_t stamp, const double* xp,
+                                           const double* up, const double* wp, double R, double* acc) {
+  bool ok[U], cli[U];
+  int code[U], q[U], qb[U], cq[U][3], y[U][2];
+  long long xg[U], yc[U];
+  T gq[U], gqb[U], gm[U];
 #pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    const int cq0 = CX[q], cq1 = CY[q], cq2 = CZ[q];
-    const int xi = wrapi(c.ii - cq0, d.nx), xj = wrapi(c.jj - cq1, d.ny), xk = wrapi(c.kk - cq2, d.nz);
-    const long long xg = cidx(d, xi, xj, xk);
-    if (c.staged) {
-      code[q] = c.st[c.cidx0 - cq0 - c.HX * (cq1 + c.HY * cq2)];
-    } else {
-      int zo = -1;
-      const int zs = new_state(d, xg, c.stamp, &zo);
-      code[q] = zs == S_WALL ? L_WALL : (zs == S_SOLID ? (zo == c.i ? L_OWN : L_OTHER) : (zs == S_SHELL ? L_SHELL : L_FLUID));
-    }
-    long long xm = xg;
-    cli[q] = false;
-    if (code[q] <= L_SHELL && d.boundary == 0) {
-      const long long xmg = cidx(d, wrapi(xi - cq0, d.nx), wrapi(xj - cq1, d.ny), wrapi(xk - cq2, d.nz));
-      if (c.staged) {
-        cli[q] = c.st[c.cidx0 - 2 * cq0 - c.HX * (2 * cq1 + c.HY * 2 * cq2)] <= L_SHELL;
-      } else {
-        int mo;
-        cli[q] = is_fluid_state(new_state(d, xmg, c.stamp, &mo));
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + u * (int)blockDim.x;
+    ok[u] = k < tot;
+    const uint32_t e = ok[u] ? lk[k] : 0u;
+    const int t = (int)(e & 0xFFFFu);
+    q[u] = (int)((e >> 16) & 31u);
+    qb[u] = (int)((e >> 21) & 31u);
+    cq[u][0] = (int)((e >> 26) & 3u) - 1;
+    cq[u][1] = (int)((e >> 28) & 3u) - 1;
+    cq[u][2] = (int)((e >> 30) & 3u) - 1;
+    const int tx = t % EX, ty = t / EX;
+    y[u][0] = d.walls[0] ? ix0 + tx : wrapmod(ix0 + tx, d.nx);
+    y[u][1] = d.walls[1] ? jy0 + ty : wrapmod(jy0 + ty, d.ny);
+    yc[u] = cidx(d, y[u][0], y[u][1], kk);
+    const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
+    // wall layers shield every non-wall cell, so y - c_q stays in range
+    const int xi = wrapi(y[u][0] - cq[u][0], d.nx), xj = wrapi(y[u][1] - cq[u][1], d.ny),
+              xk = wrapi(kk - cq[u][2], d.nz);
+    xg[u] = cidx(d, xi, xj, xk);
+    code[u] = ok[u] ? slab_code(d, st, stg, cidx0, HX, HY, cq[u], 1, xg[u], stamp, i) : L_OWN;
+    cli[u] = false;
+    gq[u] = gqb[u] = gm[u] = (T)0.0f;
+    if (code[u] <= L_SHELL) {
+      long long xmg = 0;
+      if (d.boundary == 0) {
+        xmg = cidx(d, wrapi(xi - cq[u][0], d.nx), wrapi(xj - cq[u][1], d.ny), wrapi(xk - cq[u][2], d.nz));
+        cli[u] = slab_code(d, st, stg, cidx0, HX, HY, cq[u], 2, xmg, stamp, i) <= L_SHELL;
       }
-      if (cli[q]) xm = xmg;
+      gq[u] = buf[(size_t)q[u] * N + xg[u]];
+      gqb[u] = buf[(size_t)qb[u] * N + xg[u]];
+      if (cli[u]) gm[u] = buf[(size_t)q[u] * N + xmg];
     }
-    vq[q] = c.buf[(size_t)q * c.N + xg];
-    vqb[q] = c.buf[(size_t)OPP[q] * c.N + xg];
-    vm[q] = c.buf[(size_t)q * c.N + xm];
   }
-  double val[Q];
 #pragma unroll
-  for (int q = 1; q < Q; ++q) {
-    val[q] = 0.0;
-    if (code[q] == L_OWN) continue;
-    const int cq[3] = {CX[q], CY[q], CZ[q]};
+  for (int u = 0; u < U; ++u) {
+    if (!ok[u]) continue;
+    const int* c = cq[u];
+    const double wq = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] == 1 ? 1.0 / 18 : 1.0 / 36;
     double Fq[3], arm[3];
-    if (code[q] <= L_SHELL) {
-      const double gq = raw_to_d<T>(vq[q]), gqb = raw_to_d<T>(vqb[q]), gm = raw_to_d<T>(vm[q]);
-      const int xi = wrapi(c.ii - cq[0], d.nx), xj = wrapi(c.jj - cq[1], d.ny), xk = wrapi(c.kk - cq[2], d.nz);
+    if (code[u] <= L_SHELL) {
+      const int xi = wrapi(y[u][0] - c[0], d.nx), xj = wrapi(y[u][1] - c[1], d.ny), xk = wrapi(kk - c[2], d.nz);
       double r[3];
-      r[0] = min_image(((double)xi + 0.5) - c.xp[0], d.nx, d.walls[0]);
-      r[1] = min_image(((double)xj + 0.5) - c.xp[1], d.ny, d.walls[1]);
-      r[2] = min_image(((double)xk + 0.5) - c.xp[2], d.nz, d.walls[2]);
-      const double dl = link_delta(r, cq, c.R);
-      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * cq[a];
+      r[0] = min_image(((double)xi + 0.5) - xp[0], d.nx, d.walls[0]);
+      r[1] = min_image(((double)xj + 0.5) - xp[1], d.ny, d.walls[1]);
+      r[2] = min_image(((double)xk + 0.5) - xp[2], d.nz, d.walls[2]);
+      const double dl = link_delta(r, c, R);
+      for (int a = 0; a < 3; ++a) arm[a] = r[a] + dl * c[a];
       double ub[3];
-      ub[0] = c.up[0] + (c.wp[1] * arm[2] - c.wp[2] * arm[1]);
-      ub[1] = c.up[1] + (c.wp[2] * arm[0] - c.wp[0] * arm[2]);
-      ub[2] = c.up[2] + (c.wp[0] * arm[1] - c.wp[1] * arm[0]);
-      const double dd = cli[q] ? dl : 0.5;
-      double v = gq;
-      if (cli[q]) v += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (gm - gqb);
-      v -= 4.0 / (1.0 + 2.0 * dd) * WQ[q] * 3.0 * (ub[0] * cq[0] + ub[1] * cq[1] + ub[2] * cq[2]);
-      val[q] = v;
-      const double fq = gq + WQ[q], fb = v + WQ[q];
-      for (int a = 0; a < 3; ++a) Fq[a] = (cq[a] - ub[a]) * fq - (-cq[a] - ub[a]) * fb;
+      ub[0] = up[0] + (wp[1] * arm[2] - wp[2] * arm[1]);
+      ub[1] = up[1] + (wp[2] * arm[0] - wp[0] * arm[2]);
+      ub[2] = up[2] + (wp[0] * arm[1] - wp[1] * arm[0]);
+      const double dd = cli[u] ? dl : 0.5;
+      const double vq = raw_to_d<T>(gq[u]);
+      double val = vq;
+      if (cli[u]) val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (raw_to_d<T>(gm[u]) - raw_to_d<T>(gqb[u]));
+      val -= 4.0 / (1.0 + 2.0 * dd) * wq * 3.0 * (ub[0] * c[0] + ub[1] * c[1] + ub[2] * c[2]);
+      stv<T>(buf + (size_t)qb[u] * N + yc[u], val);
+      const double fq = vq + wq, fb = val + wq;
+      for (int a = 0; a < 3; ++a) Fq[a] = (c[a] - ub[a]) * fq - (-c[a] - ub[a]) * fb;
     } else {
-      // wall or another sphere's solid: missing link, F_q = 2 w_q c_q
-      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * WQ[q] * cq[a];
-      arm[0] = min_image(((double)c.ii + 0.5) - c.xp[0], d.nx, d.walls[0]) - 0.5 * cq[0];
-      arm[1] = min_image(((double)c.jj + 0.5) - c.xp[1], d.ny, d.walls[1]) - 0.5 * cq[1];
-      arm[2] = min_image(((double)c.kk + 0.5) - c.xp[2], d.nz, d.walls[2]) - 0.5 * cq[2];
+      for (int a = 0; a < 3; ++a) Fq[a] = 2.0 * wq * c[a];
+      arm[0] = min_image(((double)y[u][0] + 0.5) - xp[0], d.nx, d.walls[0]) - 0.5 * c[0];
+      arm[1] = min_image(((double)y[u][1] + 0.5) - xp[1], d.ny, d.walls[1]) - 0.5 * c[1];
+      arm[2] = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]) - 0.5 * c[2];
     }
     acc[0] += Fq[0];
     acc[1] += Fq[1];
@@ -545,9 +554,6 @@ __device__ inline void link_all(const LinkCtx<T>& c, double* acc) {
     acc[4] += arm[2] * Fq[0] - arm[0] * Fq[2];
     acc[5] += arm[0] * Fq[1] - arm[1] * Fq[0];
   }
-#pragma unroll
-  for (int q = 1; q < Q; ++q)
-    if (code[q] <= L_SHELL) stv<T>(c.buf + (size_t)OPP[q] * c.N + c.yc, val[q]);
 }
 
 template <typename T>
@@ -579,6 +585,9 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
   const int EX = bx.ext[0], EY = bx.ext[1], HX = EX + 4, HY = COMMIT_ROWS + 4;
   const bool staged = HX * HY * 5 <= STAGE_BYTES;
   __shared__ uint8_t st[STAGE_BYTES];
+  __shared__ uint32_t lk[(Q - 1) * 256];  // one chunk's links (at most 18 per cell)
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int sl = bz; sl < bx.ext[2]; sl += d.ZB) {
     const int kz = bx.lo[2] + sl;
@@ -631,42 +640,74 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
         __syncthreads();
       }
       const int ncell = EX * nrow;
-      for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
-        const int tx = t % EX, ty = t / EX;
-        const int ii = d.walls[0] ? bx.lo[0] + tx : wrapmod(bx.lo[0] + tx, d.nx);
-        const int jj = d.walls[1] ? bx.lo[1] + ry0 + ty : wrapmod(bx.lo[1] + ry0 + ty, d.ny);
-        // only cells within the old or new shell ball of i can change through i
-        const double dn2 = cell_d2(d, ii, jj, kk, xp);
-        if (!(dn2 <= rs2) && !(cell_d2(d, ii, jj, kk, xo) <= rs2)) continue;
-        const long long yc = cidx(d, ii, jj, kk);
-        const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
-        // the cell's state: staged when its plane cuts the solid ball (then
-        // only another sphere's solid needs the claim for its owner)
-        const bool stg = staged && cuts;
-        const int sc = stg ? (int)st[cidx0] : -1;
-        int own = -1, ns;
-        if (sc == L_OWN) {
-          ns = S_SOLID;
-          own = i;
-        } else if (sc == L_SHELL || sc == L_FLUID) {
-          ns = sc == L_SHELL ? S_SHELL : S_FLUID;
-        } else if (sc == L_WALL) {
-          ns = S_WALL;
-        } else {
-          ns = new_state(d, yc, stamp, &own);
+      // the cell's state: staged when its plane cuts the solid ball (then
+      // only another sphere's solid needs the claim for its owner)
+      const bool stg = staged && cuts;
+      for (int t0 = 0; t0 < ncell; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        uint32_t mask = 0u;
+        if (t < ncell) {
+          const int tx = t % EX, ty = t / EX;
+          const int ii = d.walls[0] ? bx.lo[0] + tx : wrapmod(bx.lo[0] + tx, d.nx);
+          const int jj = d.walls[1] ? bx.lo[1] + ry0 + ty : wrapmod(bx.lo[1] + ry0 + ty, d.ny);
+          // only cells within the old or new shell ball of i can change through i
+          if (cell_d2(d, ii, jj, kk, xp) <= rs2 || cell_d2(d, ii, jj, kk, xo) <= rs2) {
+            const long long yc = cidx(d, ii, jj, kk);
+            const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
+            const int sc = stg ? (int)st[cidx0] : -1;
+            int own = -1, ns;
+            if (sc == L_OWN) {
+              ns = S_SOLID;
+              own = i;
+            } else if (sc == L_SHELL || sc == L_FLUID) {
+              ns = sc == L_SHELL ? S_SHELL : S_FLUID;
+            } else if (sc == L_WALL) {
+              ns = S_WALL;
+            } else {
+              ns = new_state(d, yc, stamp, &own);
+            }
+            if (ns != S_WALL) {
+              d.flags[yc] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
+              if (ns == S_SOLID) d.owner[yc] = own;
+            }
+            if (ns == S_SOLID && own == i) {
+              // the links of y: directions whose y - c_q is not this sphere's solid
+#pragma unroll
+              for (int q = 1; q < Q; ++q) {
+                const int c[3] = {CX[q], CY[q], CZ[q]};
+                const long long xg = stg ? 0 : cidx(d, wrapi(ii - c[0], d.nx), wrapi(jj - c[1], d.ny), wrapi(kk - c[2], d.nz));
+                if (slab_code(d, st, stg, cidx0, HX, HY, c, 1, xg, stamp, i) != L_OWN) mask |= 1u << q;
+              }
+            }
+          }
         }
-        if (ns == S_WALL) continue;
-        d.flags[yc] = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
-        if (ns == S_SOLID) d.owner[yc] = own;
-        if (!(ns == S_SOLID && own == i)) continue;
-        const LinkCtx<T> lc{d, buf, N, st, stg, cidx0, HX, HY, ii, jj, kk, yc, i, stamp, xp, up, wp, R};
-        link_all<T>(lc, acc);
+        // ordered compaction of the chunk's links (cell order, then direction)
+        const int cnt = __popc(mask);
+        int v = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int w = __shfl_up(v, o, 64);
+          if (lane >= o) v += w;
+        }
+        if (lane == 63) wsum[wid] = v;
+        __syncthreads();
+        int off = v - cnt, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+          if (w < wid) off += wsum[w];
+          tot += wsum[w];
+        }
+#pragma unroll
+        for (int q = 1; q < Q; ++q)
+          if (mask & (1u << q)) lk[off++] = link_entry(t, q);
+        __syncthreads();
+        for (int k0 = threadIdx.x; k0 < tot; k0 += LINK_UNROLL * blockDim.x)
+          slab_links<T, LINK_UNROLL>(d, buf, N, st, stg, lk, k0, tot, EX, HX, HY, bx.lo[0], bx.lo[1] + ry0, kk, i,
+                                     stamp, xp, up, wp, R, acc);
+        __syncthreads();  // the list, the wave sums and the staged states are reused
       }
     }
   }
   // fixed-order block reduction: wavefront shuffles, then across wavefronts
   __shared__ double red[6][8];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < 6; ++k) {
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -716,14 +757,7 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step, int ad
 // surface list.
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
-// A link of the ball pass, packed: cube index t of the solid cell y (bits
-// 0-15), q (16-20), qbar (21-25) and c_q + 1 per axis (26-31).
-__device__ __forceinline__ uint32_t link_entry(int t, int q) {
-  return (uint32_t)t | ((uint32_t)q << 16) | ((uint32_t)OPP[q] << 21) | ((uint32_t)(CX[q] + 1) << 26) |
-         ((uint32_t)(CY[q] + 1) << 28) | ((uint32_t)(CZ[q] + 1) << 30);
-}
 
-constexpr int BALL_LINK_UNROLL = 2;
 
 // Links k0, k0 + blockDim.x, ... (at most U of them below tot) of sphere i,
 // all loads issued before any is used.  y - c_q fluid: boundary value of
@@ -1004,8 +1038,8 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     for (int q = 1; q < Q; ++q)
       if (mask & (1u << q)) lk[off++] = link_entry(t, q);
     __syncthreads();
-    for (int k0 = threadIdx.x; k0 < tot; k0 += BALL_LINK_UNROLL * blockDim.x)
-      ball_links<T, BALL_LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
+    for (int k0 = threadIdx.x; k0 < tot; k0 += LINK_UNROLL * blockDim.x)
+      ball_links<T, LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
     __syncthreads();  // the next chunk reuses the list and the wave sums
   }
   // 5. fixed-order block reduction
