@@ -452,7 +452,8 @@ __device__ __forceinline__ uint32_t link_entry(int t, int q) {
          ((uint32_t)(CY[q] + 1) << 28) | ((uint32_t)(CZ[q] + 1) << 30);
 }
 
-constexpr int LINK_UNROLL = 2;
+constexpr int LINK_UNROLL = 2;       // links in flight per thread, slab pass
+constexpr int BALL_LINK_UNROLL = 1;  // ball pass: fewer registers, five waves per SIMD
 
 // State code of the cell z = y - m c_q seen from sphere i: from the staged
 // slab (index cidx0 of y, staged row pitch HX, HY) or from the global arrays.
@@ -1038,8 +1039,8 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     for (int q = 1; q < Q; ++q)
       if (mask & (1u << q)) lk[off++] = link_entry(t, q);
     __syncthreads();
-    for (int k0 = threadIdx.x; k0 < tot; k0 += LINK_UNROLL * blockDim.x)
-      ball_links<T, LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
+    for (int k0 = threadIdx.x; k0 < tot; k0 += BALL_LINK_UNROLL * blockDim.x)
+      ball_links<T, BALL_LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
     __syncthreads();  // the next chunk reuses the list and the wave sums
   }
   // 5. fixed-order block reduction
@@ -1059,10 +1060,11 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
 // one block per sphere, taken in the space-filling-curve order and spread over
 // the XCDs in contiguous runs, so that neighbouring spheres, whose staging
 // balls and links share cache lines, are served by the same L2.  At least
-// four waves per SIMD (at most 128 VGPRs; measured 7 % faster at 10,000
-// spheres than the three that the unconstrained allocation allows)
+// five waves per SIMD (at most 96 VGPRs, one link in flight per thread):
+// 1.66 ms at 10,000 spheres, against 1.78 ms with four waves and two links
+// and ~1.9 ms with the three waves the unconstrained allocation allows
 template <typename T>
-__global__ __launch_bounds__(BALL_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_commit_ball(DevDomain d,
+__global__ __launch_bounds__(BALL_THREADS) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_commit_ball(DevDomain d,
                                                                                              int in_step,
                                                                                              int advance) {
   const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
