@@ -107,6 +107,16 @@ __device__ inline void mapped_ball_box(const DevDomain& d, int i, Box& b) {
   }
 }
 
+// i mod n for i that is almost always within one period of [0, n): one
+// conditional wrap, the full modulo only when that does not land in range
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  if (i < 0)
+    i += n;
+  else if (i >= n)
+    i -= n;
+  return (unsigned)i < (unsigned)n ? i : wrapmod(i, n);
+}
+
 __device__ inline double cell_d2(const DevDomain& d, int i, int j, int k, const double* xp) {
 #pragma clang fp contract(off)
   const double dx = min_image(((double)i + 0.5) - xp[0], d.nx, d.walls[0]);
@@ -900,7 +910,7 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
             out = out || g[a] < 0 || g[a] >= n[a];
             ijk[a] = g[a];
           } else {
-            ijk[a] = wrapmod(g[a], n[a]);
+            ijk[a] = wrap_near(g[a], n[a]);
           }
         }
         if (out) {
@@ -947,8 +957,9 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     int ijk[3], h[3];
     bool in = true;
     for (int a = 0; a < 3; ++a) {
-      ijk[a] = d.walls[a] ? g[a] : wrapmod(g[a], n[a]);
-      h[a] = d.walls[a] ? g[a] - lo[a] : wrapmod(g[a] - lo[a], n[a]);
+      ijk[a] = d.walls[a] ? g[a] : wrap_near(g[a], n[a]);
+      h[a] = g[a] - lo[a];
+      if (!d.walls[a] && (h[a] < 0 || h[a] >= he)) h[a] = wrapmod(h[a], n[a]);
       in = in && h[a] >= 0 && h[a] < he;
     }
     if (!(cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) && !(cell_d2(d, ijk[0], ijk[1], ijk[2], xo) <= rs2))
