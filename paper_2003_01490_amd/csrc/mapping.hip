@@ -162,12 +162,12 @@ __device__ inline void stv<__half>(__half* p, double v) { *p = __float2half_rn((
 // iterate the cells of a box: slabs of sphere-block b, threads over x-y
 #define FOR_BOX_CELLS(d, bx, b, ZB, ...)                                             \
   for (int sl = (b); sl < (bx).ext[2]; sl += (ZB)) {                                 \
-    const int kk = (d).walls[2] ? (bx).lo[2] + sl : wrapmod((bx).lo[2] + sl, (d).nz); \
+    const int kk = (d).walls[2] ? (bx).lo[2] + sl : wrap_near((bx).lo[2] + sl, (d).nz); \
     const int nxy_ = (bx).ext[0] * (bx).ext[1];                                      \
     for (int t = threadIdx.x; t < nxy_; t += blockDim.x) {                           \
       const int tx = t % (bx).ext[0], ty = t / (bx).ext[0];                          \
-      const int ii = (d).walls[0] ? (bx).lo[0] + tx : wrapmod((bx).lo[0] + tx, (d).nx); \
-      const int jj = (d).walls[1] ? (bx).lo[1] + ty : wrapmod((bx).lo[1] + ty, (d).ny); \
+      const int ii = (d).walls[0] ? (bx).lo[0] + tx : wrap_near((bx).lo[0] + tx, (d).nx); \
+      const int jj = (d).walls[1] ? (bx).lo[1] + ty : wrap_near((bx).lo[1] + ty, (d).ny); \
       __VA_ARGS__                                                                    \
     }                                                                                \
   }
@@ -504,8 +504,8 @@ __device__ __forceinline__ void slab_links(const DevDomain& d, T* buf, size_t N,
     cq[u][1] = (int)((e >> 28) & 3u) - 1;
     cq[u][2] = (int)((e >> 30) & 3u) - 1;
     const int tx = t % EX, ty = t / EX;
-    y[u][0] = d.walls[0] ? ix0 + tx : wrapmod(ix0 + tx, d.nx);
-    y[u][1] = d.walls[1] ? jy0 + ty : wrapmod(jy0 + ty, d.ny);
+    y[u][0] = d.walls[0] ? ix0 + tx : wrap_near(ix0 + tx, d.nx);
+    y[u][1] = d.walls[1] ? jy0 + ty : wrap_near(jy0 + ty, d.ny);
     yc[u] = cidx(d, y[u][0], y[u][1], kk);
     const int cidx0 = (tx + 2) + HX * ((ty + 2) + HY * 2);
     // wall layers shield every non-wall cell, so y - c_q stays in range
@@ -602,7 +602,7 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int sl = bz; sl < bx.ext[2]; sl += d.ZB) {
     const int kz = bx.lo[2] + sl;
-    const int kk = d.walls[2] ? kz : wrapmod(kz, d.nz);
+    const int kk = d.walls[2] ? kz : wrap_near(kz, d.nz);
     // does this plane cut the new solid ball of sphere i?
     const double dzc = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]);
     const bool cuts = dzc * dzc <= R2;
@@ -626,7 +626,7 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
             in[u] = t < NS && (!d.walls[0] || (gx >= 0 && gx < d.nx)) &&
                     (!d.walls[1] || (gy >= 0 && gy < d.ny)) && (!d.walls[2] || (gz >= 0 && gz < d.nz));
             if (in[u]) {
-              const long long c = cidx(d, wrapmod(gx, d.nx), wrapmod(gy, d.ny), wrapmod(gz, d.nz));
+              const long long c = cidx(d, wrap_near(gx, d.nx), wrap_near(gy, d.ny), wrap_near(gz, d.nz));
               fl[u] = d.flags[c];
               kc[u] = d.claim[c];
               ss[u] = d.shellstamp[c];
@@ -659,8 +659,8 @@ __device__ __forceinline__ void commit_block(const DevDomain& d, int blk, int cu
         uint32_t mask = 0u;
         if (t < ncell) {
           const int tx = t % EX, ty = t / EX;
-          const int ii = d.walls[0] ? bx.lo[0] + tx : wrapmod(bx.lo[0] + tx, d.nx);
-          const int jj = d.walls[1] ? bx.lo[1] + ry0 + ty : wrapmod(bx.lo[1] + ry0 + ty, d.ny);
+          const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
+          const int jj = d.walls[1] ? bx.lo[1] + ry0 + ty : wrap_near(bx.lo[1] + ry0 + ty, d.ny);
           // only cells within the old or new shell ball of i can change through i
           if (cell_d2(d, ii, jj, kk, xp) <= rs2 || cell_d2(d, ii, jj, kk, xo) <= rs2) {
             const long long yc = cidx(d, ii, jj, kk);
@@ -796,9 +796,9 @@ __device__ __forceinline__ void ball_links(const DevDomain& d, T* buf, size_t N,
     cq[u][1] = (int)((e >> 28) & 3u) - 1;
     cq[u][2] = (int)((e >> 30) & 3u) - 1;
     const int h[3] = {t % he, (t / he) % he, t / (he * he)};
-    y[u][0] = d.walls[0] ? lo[0] + h[0] : wrapmod(lo[0] + h[0], d.nx);
-    y[u][1] = d.walls[1] ? lo[1] + h[1] : wrapmod(lo[1] + h[1], d.ny);
-    y[u][2] = d.walls[2] ? lo[2] + h[2] : wrapmod(lo[2] + h[2], d.nz);
+    y[u][0] = d.walls[0] ? lo[0] + h[0] : wrap_near(lo[0] + h[0], d.nx);
+    y[u][1] = d.walls[1] ? lo[1] + h[1] : wrap_near(lo[1] + h[1], d.ny);
+    y[u][2] = d.walls[2] ? lo[2] + h[2] : wrap_near(lo[2] + h[2], d.nz);
     const int off = cq[u][0] + he * (cq[u][1] + he * cq[u][2]);
     code[u] = ok[u] ? (int)st[t - off] : L_OWN;
     cli[u] = false;
