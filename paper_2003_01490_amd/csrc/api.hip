@@ -721,7 +721,7 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
     auto dem = [&] {
       timed(dom, 1, ds, [&] {
         e = launch_dem(dom->d, dom->cfg.dem_kernel, !dom->may_prescribe, ds);
-        launch_claim(dom->d, 1, ds);
+        launch_claim(dom->d, 1, dem_many(dom->d, dom->cfg.dem_kernel), ds);
       });
     };
     if (!ov) {

@@ -269,7 +269,9 @@ void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s);
 // the claim kernel alone (needs only the particle positions), and the rest;
 // in_step = 1 inside a step (after the sweep and the DEM, before the step
 // control), 0 for an update outside the step
-void launch_claim(const DevDomain& d, int in_step, hipStream_t s);
+// lists: the step's many-sphere neighbour lists are valid (claims of spheres
+// that meet no other sphere then need no atomics)
+void launch_claim(const DevDomain& d, int in_step, bool lists, hipStream_t s);
 void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s);
 // the same inside a step, ending with the step control (folded into the last
 // block of the boundary pass, or its own kernel when there is none)

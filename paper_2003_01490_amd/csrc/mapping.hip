@@ -172,9 +172,34 @@ __device__ inline void stv<__half>(__half* p, double v) { *p = __float2half_rn((
     }                                                                                \
   }
 
-__device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_t stamp) {
+// Claims of sphere i's solid cells with a stamped key; the largest key (this
+// stamp, lowest id) wins a cell inside several spheres.  With `lists` (the
+// neighbour lists of this step are valid: the many-sphere DEM built them from
+// the positions at the start of the step with a skin, so they hold every
+// sphere that can touch i now), a sphere whose ball meets no other claims its
+// cells with plain stores: no other sphere claims them, and every older key
+// is smaller.
+__device__ __forceinline__ bool claims_exclusive(const DevDomain& d, int i) {
+  const int nn = d.p.nbr_n[i];
+  if (nn >= NBR_MAX) return false;  // a list that overflowed may miss a neighbour
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int k = 0; k < nn; ++k) {
+    const int j = d.p.nbr[(size_t)i * NBR_MAX + k];
+    double s2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double v = min_image(d.p.x[3 * i + a] - d.p.x[3 * j + a], n[a], d.walls[a]);
+      s2 += v * v;
+    }
+    // balls that are 1e-6 apart share no cell centre, whatever the rounding
+    if (!(sqrt(s2) - (d.p.R[i] + d.p.R[j]) >= 1e-6)) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_t stamp, bool lists) {
   const int i = blk / d.ZB, b = blk % d.ZB;
   if (i >= d.P) return;
+  const bool excl = lists && claims_exclusive(d, i);
   Box bx;
   sphere_box(d, i, false, bx);
   const double xp[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
@@ -192,7 +217,12 @@ __device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_
     const long long c = cidx(d, ii, jj, kk);
     if (!(d.flags[c] & F_WALL)) {
       const double d2 = cell_d2(d, ii, jj, kk, xp);
-      if (d2 <= R2) atomicMax(&d.claim[c], key);
+      if (d2 <= R2) {
+        if (excl)
+          d.claim[c] = key;
+        else
+          atomicMax(&d.claim[c], key);
+      }
       if (d2 <= rs2) d.shellstamp[c] = stamp;
     }
   })
@@ -208,10 +238,10 @@ __device__ __forceinline__ bool map_live(const DevCtl* c, int in_step) {
 __device__ __forceinline__ int map_buffer(const DevCtl* c, int in_step) { return c->cur ^ (in_step ? 1 : 0); }
 __device__ __forceinline__ uint32_t map_stamp(const DevCtl* c) { return c->stamp + 1u; }
 
-__global__ __launch_bounds__(256) void k_claim(DevDomain d, int in_step) {
+__global__ __launch_bounds__(256) void k_claim(DevDomain d, int in_step, int lists) {
   __builtin_amdgcn_s_setprio(3);  // runs beside the sweep in an overlapped step
   if (!map_live(d.ctl, in_step)) return;
-  claim_block(d, blockIdx.x, map_stamp(d.ctl));
+  claim_block(d, blockIdx.x, map_stamp(d.ctl), lists != 0);
 }
 
 // the new stamp after a mapping update outside the step
@@ -1084,9 +1114,9 @@ __global__ __launch_bounds__(BALL_THREADS) __attribute__((amdgpu_waves_per_eu(5,
 }
 
 
-void launch_claim(const DevDomain& d, int in_step, hipStream_t s) {
+void launch_claim(const DevDomain& d, int in_step, bool lists, hipStream_t s) {
   const int nsb = d.P * d.ZB;
-  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, in_step);
+  if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, in_step, (in_step && lists) ? 1 : 0);
 }
 
 template <typename T>
@@ -1127,7 +1157,7 @@ void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_
 void launch_update_and_advance(const DevDomain& d, hipStream_t s) { launch_update_any(d, true, 1, 1, s); }
 
 void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
-  launch_claim(d, 0, s);
+  launch_claim(d, 0, false, s);
   launch_update(d, reconstruct, 0, s);
   hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
 }
@@ -1139,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_claim_batch(const DevDomain* __restrict
   const int k = batch_domain(start, ndom, (int)blockIdx.x);
   const DevDomain& d = tab[k];
   if (!step_live(d.ctl)) return;
-  claim_block(d, (int)blockIdx.x - start[k], map_stamp(d.ctl));
+  claim_block(d, (int)blockIdx.x - start[k], map_stamp(d.ctl), false);
 }
 
 template <typename T>
