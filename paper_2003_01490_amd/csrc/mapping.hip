@@ -213,9 +213,13 @@ __device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_
   }
   const unsigned long long key =
       ((unsigned long long)stamp << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+  // wall layers (the first and last layer of a walled axis) are never
+  // claimed; they are known from the coordinates, so no flag is read
   FOR_BOX_CELLS(d, bx, b, d.ZB, {
     const long long c = cidx(d, ii, jj, kk);
-    if (!(d.flags[c] & F_WALL)) {
+    const bool wall = (d.walls[0] && (ii == 0 || ii == d.nx - 1)) || (d.walls[1] && (jj == 0 || jj == d.ny - 1)) ||
+                      (d.walls[2] && (kk == 0 || kk == d.nz - 1));
+    if (!wall) {
       const double d2 = cell_d2(d, ii, jj, kk, xp);
       if (d2 <= R2) {
         if (excl)
