@@ -28,6 +28,12 @@
  *   - contact active for a negative gap, no clamping of the normal force;
  *   - velocity-dependent forces use the velocities before the sub-step update;
  *   - reconstruction neighbours: fluid before and after the mapping update.
+ *
+ * Pins (tests/test_oracle_*.py) check every part against closed forms,
+ * invariants, exact arithmetic or hand-derived values.  Parity unpinned (a
+ * convention with nothing outside the oracle to check it against): the
+ * first-step averaging, the geometry of the bounce-back fallback, and the
+ * unequal-radius choices for T_c, delta_min and the contact point.
  */
 #include "lbmdem_ref.h"
 

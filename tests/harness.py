@@ -92,3 +92,31 @@ def random_pdf(n, seed, amp=0.02, u0=(0.0, 0.0, 0.0)):
     feq = O.equilibrium(1.0, np.asarray(u0, dtype=float))
     f = feq[:, None, None, None] * (1.0 + amp * rng.standard_normal((19, nz, ny, nx)))
     return f
+
+
+def exact_tie_counts(n, walls, spheres, delta_ab=2.0, scale=1 << 11):
+    """Exact counts of cell centres lying on a sphere surface (d^2 == R^2), on a
+    shell surface (d^2 == (R + delta_aB)^2), and inside or on two solid balls."""
+    on_surface = on_shell = shared = 0
+    for k in range(n[2]):
+        for j in range(n[1]):
+            for i in range(n[0]):
+                ijk = (i, j, k)
+                inside = 0
+                for x, R in spheres:
+                    d2 = 0
+                    for a in range(3):
+                        v = (2 * ijk[a] + 1) * (scale // 2) - int(round(x[a] * scale))
+                        if not walls[a]:
+                            L = n[a] * scale
+                            if 2 * v > L:
+                                v -= L
+                            elif 2 * v < -L:
+                                v += L
+                        d2 += v * v
+                    Ri, Rs = int(round(R * scale)), int(round((R + delta_ab) * scale))
+                    on_surface += d2 == Ri * Ri
+                    on_shell += d2 == Rs * Rs
+                    inside += d2 <= Ri * Ri
+                shared += inside >= 2
+    return on_surface, on_shell, shared

@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 from paper_2003_01490_amd import workloads as W
 
-from harness import Scales, gpu_domain, oracle_domain, random_pdf, sphere_errs, weight
+from harness import Scales, exact_tie_counts, gpu_domain, oracle_domain, random_pdf, sphere_errs, weight
 
 pytestmark = pytest.mark.gpu
 
@@ -207,15 +207,23 @@ def test_mapping_bit_exact(storage):
     _case(f"mapping {n} storage {storage}")
     rng = np.random.default_rng(5)
     xs, Rs = [], []
-    # dyadic centres so that cell centres fall exactly on some surfaces
-    cand = [([7.0, 7.5, 8.0], 2.5), ([29.75, 14.0, 12.5], 3.0), ([15.0, 27.5, 20.0], 3.25)]
+    # centres on cell centres with Pythagorean radii: cell centres lie exactly
+    # on the R = 5 and R = 3 surfaces and on the R + delta_aB shell surfaces,
+    # and the two R = 5 spheres touch at one cell centre (owner: lower id)
+    cand = [([10.5, 10.5, 10.5], 5.0), ([20.5, 10.5, 10.5], 5.0), ([5.5, 20.5, 18.5], 3.0)]
+    on_surface, on_shell, shared = exact_tie_counts(n, (0, 0, 1), cand)
+    assert on_surface >= 60 and on_shell >= 100 and shared == 1
     for x, R in cand:
         xs.append(x)
         Rs.append(R)
     while len(xs) < 9:
         R = rng.uniform(1.2, 3.5)
         x = [rng.uniform(0, n[0]), rng.uniform(0, n[1]), rng.uniform(1.5 + R, n[2] - 1.5 - R)]
-        ok = all(np.linalg.norm(np.array(x) - np.array(y)) > R + r + 0.05 for y, r in zip(xs, Rs))
+        def dist(y):
+            v = np.array(x) - np.array(y)
+            v[:2] -= np.round(v[:2] / np.array(n[:2])) * np.array(n[:2])  # periodic x, y
+            return np.linalg.norm(v)
+        ok = all(dist(y) > R + r + 0.05 for y, r in zip(xs, Rs))
         if ok:
             xs.append(x)
             Rs.append(R)
@@ -228,6 +236,7 @@ def test_mapping_bit_exact(storage):
     assert np.array_equal(cg, co)
     sol = co == O.SOLID
     assert sol.sum() > 100 and np.array_equal(og[sol], oo[sol])
+    assert co[10, 10, 15] == O.SOLID and og[10, 10, 15] == 0  # the shared tie cell
 
 
 def test_fixed_sphere_forces_on_random_field():

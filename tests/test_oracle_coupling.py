@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from harness import exact_tie_counts as _tie_counts
 
 
 def _exact_flags(n, walls, spheres, delta_ab=2.0, scale=1 << 11):
@@ -59,6 +60,38 @@ def _exact_flags(n, walls, spheres, delta_ab=2.0, scale=1 << 11):
     return code, owner
 
 
+# Centres on cell centres with Pythagorean radii: offsets such as (3, 4, 0) and
+# (5, 0, 0) put cell centres exactly on the R = 5 surface, (2, 3, 6) and
+# (7, 0, 0) exactly on the R + delta_aB = 7 shell surface, and the two R = 5
+# spheres touch at one cell centre, which lies on both surfaces.
+TIE_LATTICE = (26, 21, 22)
+TIE_SPHERES = [((10.5, 10.5, 10.5), 5.0), ((20.5, 10.5, 10.5), 5.0), ((5.5, 17.5, 16.5), 3.0)]
+
+
+def test_mapping_ties_closed_ball_and_lowest_id():
+    """Sec. 2.2: a cell is solid when its centre is contained in the particle,
+    read as the closed ball (d^2 <= R^2); the TRT+aB shell is closed as well;
+    a cell centre on two spheres belongs to the lower id."""
+    n, walls = TIE_LATTICE, (0, 0, 1)
+    cfg = O.make_config(nx=n[0], ny=n[1], nz=n[2], walls=walls, max_spheres=3)
+    d = O.RefDomain(cfg)
+    for x, R in TIE_SPHERES:
+        d.add_sphere(x, R, 2.0)
+    on_surface, on_shell, shared = _tie_counts(n, walls, TIE_SPHERES)
+    assert on_surface >= 60 and on_shell >= 100 and shared == 1
+    code, owner = d.flags()
+    ecode, eowner = _exact_flags(n, walls, TIE_SPHERES)
+    assert np.array_equal(code, ecode)
+    sol = ecode == O.SOLID
+    assert np.array_equal(owner[sol], eowner[sol])
+    # surface cells are solid (closed ball), shell-surface cells are shell
+    assert code[10, 14, 13] == O.SOLID and code[10, 10, 5] == O.SOLID     # (3, 4, 0) and (-5, 0, 0)
+    assert code[10, 10, 3] == O.SHELL and code[16, 13, 12] == O.SHELL     # (-7, 0, 0) and (2, 3, 6)
+    assert code[10, 10, 2] == O.FLUID                                      # just outside the shell
+    # the touching cell (15, 10, 10) is on both surfaces: the lower id owns it
+    assert code[10, 10, 15] == O.SOLID and owner[10, 10, 15] == 0
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_mapping_matches_exact_integer_classification(seed):
     rng = np.random.default_rng(seed)
@@ -67,15 +100,11 @@ def test_mapping_matches_exact_integer_classification(seed):
     cfg = O.make_config(nx=n[0], ny=n[1], nz=n[2], walls=walls, max_spheres=3)
     d = O.RefDomain(cfg)
     spheres = []
-    # includes ties: R and offsets on the 2^-10 grid so d^2 == R^2 happens
+    # random dyadic placements (ties are covered by the placements above)
     for sid in range(3):
         for _ in range(200):
             R = rng.integers(1 * 1024, 3 * 1024) / 1024.0
-            if sid == 0:
-                R = 2.5
             x = [rng.integers(0, n[a] * 1024) / 1024.0 for a in range(3)]
-            if sid == 0:
-                x = [5.0, 5.5, 6.0]  # several cells exactly on the surface
             if d.try_add_sphere(x, R, 2.0) >= 0:
                 spheres.append((x, R))
                 break
@@ -84,7 +113,6 @@ def test_mapping_matches_exact_integer_classification(seed):
     assert np.array_equal(code, ecode)
     sol = ecode == O.SOLID
     assert np.array_equal(owner[sol], eowner[sol])
-    # the tie case really happens: cells with d^2 == R^2 exist and are solid
     assert (code == O.SOLID).sum() > 0
 
 
@@ -194,6 +222,103 @@ def test_reconstruction_at_rest_gives_weights():
     assert newly.sum() > 5
     pdf = d.field("pdf")
     assert np.abs(pdf[:, newly] - w[:, None]).max() < 1e-16
+
+
+def _designed_linear_field(n, x0, rho_grad, u0, G):
+    """Equilibrium distributions of a density and a velocity that are linear in
+    the cell-centre position: rho = 1 + a.(x - x0), u = u0 + G (x - x0)."""
+    c, w, _ = O.lattice()
+    nx, ny, nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.stack([i + 0.5 - x0[0], j + 0.5 - x0[1], k + 0.5 - x0[2]])
+    rho = 1.0 + np.einsum("a,a...->...", rho_grad, r)
+    u = np.asarray(u0)[:, None, None, None] + np.einsum("ab,b...->a...", G, r)
+    cu = np.einsum("qa,a...->q...", c.astype(float), u)
+    usq = (u * u).sum(0)
+    return w[:, None, None, None] * (rho + 3 * cu + 4.5 * cu * cu - 1.5 * usq)
+
+
+def test_reconstruction_gradient_term():
+    """Eq. (PDF_reconstruction) with a non-zero velocity gradient.  The fluid
+    around a sphere carries a density and a velocity linear in space (central
+    differences of it are exact); the sphere is moved so that cells are
+    uncovered.  Each rebuilt cell must (a) have the moments the formula is
+    built to have: sum f = rho_bar (mean density of the neighbours fluid before
+    and after), sum f c = rho_bar u_t (u_t the rigid-body velocity there) and
+    sum f c c = rho_bar c_s^2 I + rho_bar u_t u_t - (rho_bar c_s^2 / s_nu)
+    (G + G^T) (the Chapman-Enskog form of the viscous stress), with G from
+    central differences of the neighbour velocities, or one-sided ones
+    against u_t where a neighbour is missing, as Sec. 2.2 states; and (b)
+    f_q / w_q must be a polynomial of degree two in c_q (a second-order
+    Hermite form): together these fix all 19 values."""
+    n = (20, 20, 20)
+    cfg = O.make_config(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.03, max_spheres=1)
+    s_nu = O.rates(cfg)[0]
+    c, w, _ = O.lattice()
+    cf = c.astype(float)
+    d = O.RefDomain(cfg)
+    x_old = np.array([9.7, 10.2, 10.1])
+    sid = d.add_sphere(x_old, 3.3, 2.0)
+    d.set_mode(sid, O.MODE_FIXED)
+    G = np.array([[2e-3, -1e-3, 5e-4], [1.5e-3, -4e-4, 2e-3], [-7e-4, 1e-3, 1.2e-3]])
+    f = _designed_linear_field(n, x_old, np.array([1e-3, -5e-4, 2e-4]), (0.01, -0.005, 0.002), G)
+    d.set_pdf(f)
+    code0, _ = d.flags()
+    x_new = x_old + np.array([0.8, -0.6, 0.5])
+    u_s, w_s = np.array([0.004, -0.002, 0.003]), np.array([1e-3, -2e-3, 5e-4])
+    d.update_sphere(sid, x=x_new, u=u_s, w=w_s)
+    code1, _ = d.flags()
+    pdf = d.field("pdf")
+    fluid_both = (code0 <= O.SHELL) & (code1 <= O.SHELL)
+    rebuilt = np.argwhere((code0 == O.SOLID) & (code1 <= O.SHELL))
+    assert len(rebuilt) > 10
+    rho_f = f.sum(0)
+    j_f = np.einsum("qa,q...->a...", cf, f)
+    kinds = set()
+    grad_term = 0.0
+    # quadratic monomials of c: 1, c_a, c_a c_b (a <= b) -> 10 basis columns
+    basis = np.column_stack([np.ones(19)] + [cf[:, a] for a in range(3)] +
+                            [cf[:, a] * cf[:, b] for a in range(3) for b in range(a, 3)])
+    for k, j, i in rebuilt:
+        def nb(di, dj, dk):
+            return (k + dk) % n[2], (j + dj) % n[1], (i + di) % n[0]
+        valid = [nb(*c[q]) for q in range(1, 19) if fluid_both[nb(*c[q])]]
+        rb = np.mean([rho_f[v] for v in valid]) if valid else 1.0
+        r = np.array([i + 0.5, j + 0.5, k + 0.5]) - x_new
+        ut = u_s + np.cross(w_s, r)
+        Gm = np.zeros((3, 3))  # Gm[a, b] = d u_a / d x_b
+        for b in range(3):
+            e = np.zeros(3, dtype=int)
+            e[b] = 1
+            p, m = nb(*e), nb(*(-e))
+            vp, vm = fluid_both[p], fluid_both[m]
+            if vp and vm:
+                Gm[:, b] = 0.5 * (j_f[(slice(None),) + p] - j_f[(slice(None),) + m])
+                kinds.add("central")
+            elif vp:
+                Gm[:, b] = j_f[(slice(None),) + p] - ut
+                kinds.add("one-sided")
+            elif vm:
+                Gm[:, b] = ut - j_f[(slice(None),) + m]
+                kinds.add("one-sided")
+        fr = pdf[:, k, j, i]
+        S = Gm + Gm.T
+        assert abs(fr.sum() - rb) < 1e-15
+        np.testing.assert_allclose(cf.T @ fr, rb * ut, rtol=0, atol=1e-16)
+        second = np.einsum("q,qa,qb->ab", fr, cf, cf)
+        expect2 = rb / 3.0 * np.eye(3) + rb * np.outer(ut, ut) - rb / (3.0 * s_nu) * S
+        np.testing.assert_allclose(second, expect2, rtol=0, atol=2e-16)
+        coef, res, *_ = np.linalg.lstsq(basis, fr / w, rcond=None)
+        assert np.abs(basis @ coef - fr / w).max() < 1e-13
+        grad_term = max(grad_term, np.abs(rb / (3.0 * s_nu) * S).max())
+        # the same values, from the formula as the paper prints it
+        H = np.einsum("qa,qb->qab", cf, cf) - np.eye(3) / 3.0
+        P = rb * np.outer(ut, ut) - rb / (3.0 * s_nu) * S
+        direct = w * (rb + 3 * rb * (cf @ ut) + 4.5 * np.einsum("qab,ab->q", H, P))
+        np.testing.assert_allclose(fr, direct, rtol=0, atol=5e-16)
+    assert kinds == {"central", "one-sided"}
+    # the gradient term is exercised (far above rounding)
+    assert grad_term > 1e-4
 
 
 def test_momentum_balance_of_fixed_sphere_in_forced_flow():

@@ -239,3 +239,125 @@ def test_prescribed_ramp_and_release_at_the_wall_ahead():
         assert s["u"][2] == pytest.approx(-u_s * (1.0 - np.exp(-c_acc * k / t_st)), rel=1e-12)
     assert released_at is not None, "never released above the bottom wall"
     assert released_at[1] < gap_r
+
+
+LUB = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lubrication_coefficients.json")))
+
+
+def _frac(s):
+    a, _, b = s.partition("/")
+    return float(a) / float(b or 1)
+
+
+def _perp_frame(rng):
+    n = rng.standard_normal(3)
+    n /= np.linalg.norm(n)
+    t = np.cross(n, rng.standard_normal(3))
+    t /= np.linalg.norm(t)
+    return n, t, np.cross(n, t)
+
+
+@pytest.mark.parametrize("case", range(len(LUB["cases"]) + 1))
+def test_lubrication_coefficients_at_fixed_radius_ratios(case):
+    """D3: the pair corrections of Sec. 3.1 at kappa_r = 1, 2 and 1/2 (and the
+    sphere-wall limit) against coefficients worked out by hand from the
+    printed expressions (tests/golden/lubrication_coefficients.json), term by
+    term: a normal approach gives only the normal force, a tangential
+    translation only the tt force and torque, rotations only the tr force and
+    torque, with the rotation about the line of centres dropped from the
+    torque."""
+    wall = case == len(LUB["cases"])
+    cf = LUB["wall"] if wall else LUB["cases"][case]
+    cut_n, cut_t, cut_r = 2.0 / 3.0, 0.5, 0.45
+    cfg = O.make_config(nx=60, ny=60, nz=60, walls=(0, 0, 1), nu=0.07, dmin=0.001,
+                        cut_n=cut_n, cut_tt=cut_t, cut_tr=cut_r)
+    mu = cfg.nu
+    rng = np.random.default_rng(11 + case)
+    Ri, gap = 3.0, 0.2
+    if wall:
+        n, t, s = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+        xi = np.array([30.0, 30.0, 1.0 + Ri + gap])
+        kw = dict(wall=4)
+    else:
+        n, t, s = _perp_frame(rng)
+        Rj = Ri * _frac(cf["kappa"])
+        xj = np.array([30.0, 30.0, 30.0])
+        xi = xj + (Ri + Rj + gap) * n
+        kw = dict(xj=xj, Rj=Rj, wall=-1)
+    z = np.zeros(3)
+    Ln, Lt, Lr = 1.0 / gap - 1.0 / cut_n, np.log(gap / cut_t), np.log(gap / cut_r)
+
+    def lub(ui=z, wi=z, uj=z, wj=z):
+        return O.lubrication(cfg, xi, ui, wi, Ri, uj=uj, wj=wj, **kw)
+
+    # normal approach
+    a = 0.013
+    F, T = lub(ui=a * n)
+    np.testing.assert_allclose(F, -6 * np.pi * mu * Ri ** 2 * _frac(cf["normal"]) * Ln * a * n, rtol=1e-13, atol=1e-18)
+    assert np.abs(T).max() < 1e-15  # u_ij x n vanishes up to rounding
+    # tangential translation (relative velocity of the pair)
+    b = 0.021
+    uj = z if wall else 0.5 * b * t
+    F, T = lub(ui=1.5 * b * t, uj=uj)
+    urel = 1.5 * b * t - uj
+    np.testing.assert_allclose(F, 6 * np.pi * mu * Ri * _frac(cf["tt_force"]) * Lt * urel, rtol=1e-13, atol=1e-18)
+    np.testing.assert_allclose(T, 8 * np.pi * mu * Ri ** 2 * _frac(cf["tt_torque"]) * Lt * np.cross(urel, n),
+                               rtol=1e-13, atol=1e-18)
+    # rotations, including a component about the line of centres
+    wi = 0.004 * t - 0.003 * s + 0.002 * n
+    wj = z if wall else -0.001 * t + 0.005 * s - 0.003 * n
+    F, T = lub(wi=wi, wj=wj)
+    va, vb = (_frac(v) for v in cf["tr_force_vector"])
+    expF = -6 * np.pi * mu * Ri ** 2 * _frac(cf["tr_force"]) * Lr * np.cross(va * wi + vb * wj, n)
+    av = wi + _frac(cf["tr_torque_wj"]) * wj
+    expT = 8 * np.pi * mu * Ri ** 3 * _frac(cf["tr_torque"]) * Lr * (av - av.dot(n) * n)
+    np.testing.assert_allclose(F, expF, rtol=1e-13, atol=1e-18)
+    np.testing.assert_allclose(T, expT, rtol=1e-13, atol=1e-18)
+
+
+def test_tangential_stick_branch_rolls_without_slipping():
+    """Stick branch of the tangential contact (Sec. 4.1.2).  A sphere resting on
+    the wall under gravity is given a tangential velocity v0; with a large
+    friction coefficient the contact sticks.  While it sticks, the contact-point
+    velocity v = u_x - R_c w_y (R_c = R + delta/2 the arm to the contact point)
+    obeys m_t dv/dt = -k_t s - d_t v, ds/dt = v, with k_t = kappa_p k_n and
+    d_t = sqrt(kappa_p) d_n (Eq. tangentialCollisionParameters, k_n and d_n of
+    Eq. normalDEMparameters) and the effective mass m_t = 1 / (1/m + R_c^2 / I):
+    a damped oscillator from v(0) = v0, s(0) = 0.  The tangential impulse acts on
+    u and w with the same arm, so m u R_c + I w_y is conserved and the sphere
+    ends rolling at u = v0 / (1 + I / (m R_c^2)) (5/7 v0 for R_c = R)."""
+    R, rho, e, Tc, nu_p, g = 4.0, 2.0, 0.3, 40.0, 0.23, 1e-4
+    n = 40
+    cfg = O.make_config(nx=n, ny=n, nz=n, walls=(0, 0, 1), e_dry=e, tc=Tc, n_sub=10, friction=100.0,
+                        poisson_ratio=nu_p, lub_mask=0, gravity=(0.0, 0.0, -g), max_spheres=1)
+    d = O.RefDomain(cfg)
+    sid = d.add_sphere((n / 2, n / 2, 1.0 + R), R, rho)     # touching the wall plane
+    for _ in range(2000):                                     # settle onto the spring
+        d.dem_step()
+    s = d.sphere(sid)
+    assert abs(s["u"][2]) < 1e-12 and s["F_col"][2] > 0
+    delta = s["x"][2] - 1.0 - R
+    Rc = R + 0.5 * delta
+    m = rho * 4.0 / 3.0 * np.pi * R ** 3
+    I = 0.4 * m * R * R
+    kn = m * (np.pi ** 2 + np.log(e) ** 2) / Tc ** 2
+    dn = -2.0 * m * np.log(e) / Tc
+    kp = 2.0 * (1.0 - nu_p) / (2.0 - nu_p)
+    mt = 1.0 / (1.0 / m + Rc * Rc / I)
+    w0, gam = np.sqrt(kp * kn / mt), np.sqrt(kp) * dn / (2.0 * mt)
+    wd = np.sqrt(w0 * w0 - gam * gam)
+    v0 = 1e-3
+    d.update_sphere(sid, u=(v0, 0.0, 0.0), w=(0.0, 0.0, 0.0))
+    err = 0.0
+    for k in range(1, 61):                                    # about one oscillation period
+        d.dem_step()
+        s = d.sphere(sid)
+        v = s["u"][0] - Rc * s["w"][1]
+        expect = v0 * np.exp(-gam * k) * (np.cos(wd * k) - gam / wd * np.sin(wd * k))
+        err = max(err, abs(v - expect))
+    assert err < 0.01 * v0
+    for _ in range(600):
+        d.dem_step()
+    s = d.sphere(sid)
+    assert abs(s["u"][0] - Rc * s["w"][1]) < 1e-9 * v0
+    assert s["u"][0] == pytest.approx(v0 / (1.0 + I / (m * Rc * Rc)), rel=1e-6)
