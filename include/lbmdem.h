@@ -207,6 +207,20 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
  * reads NaN.  At most N/4 points per call (LBMDEM_EINVAL beyond). */
 int32_t lbmdem_probe_density(lbmdem_domain* dom, int32_t n, const double* xyz, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the density
+ * probe of lbmdem_probe_density with the points and results staged in a
+ * static device array of the library (at most 65536 points per call; 2 MiB
+ * held on each GPU the library runs on until the process ends) instead of the
+ * domain region.  xyz (3n doubles) and out (n doubles) are DEVICE arrays; the
+ * copies and the probe are enqueued on the domain's stream and the call
+ * returns without waiting (results are ready once that stream has reached
+ * them, e.g. after lbmdem_sync).  It calls no allocating routine.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other domains, other threads) race.  LBMDEM_EINVAL for n > 65536
+ * or NULL arrays. */
+int32_t lbmdem_probe_density_static(lbmdem_domain* dom, int32_t n, const double* xyz, double* out);
+
 /* Overwrites all PDFs with the full distributions f (host, double[19N],
  * q-major), rounded to the storage precision, and recomputes the boundary
  * values of the next step. */

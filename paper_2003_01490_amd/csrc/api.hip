@@ -5,6 +5,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -213,6 +214,7 @@ struct lbmdem_domain {
   std::vector<hipEvent_t> spare;
   double ms[3] = {0, 0, 0};
   int64_t cnt[3] = {0, 0, 0};
+  int device = 0;                     // HIP device current at creation
   lbmdem_batch* batch = nullptr;      // batch the domain is admitted to
   bool may_prescribe = false;         // a sphere was given prescribed motion (or state restored)
   // second stream of an overlapped step (created on first use) and the events
@@ -325,6 +327,38 @@ static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
   return LBMDEM_OK;
 }
 
+// ---- static device scratch of the allocation-free probe ----------------------
+// Staging of lbmdem_probe_density_static: the probe points and their results
+// live in this file-scope device array instead of the domain region.  Each
+// GPU holds its own copy for the life of the process.  In host code the name
+// `scratch` is only a host-side stand-in: its device address is looked up once
+// per device, with that device current, when a domain is created there, and
+// only that address is ever passed to kernels or copies.
+constexpr int PROBE_STATIC_MAX = 65536;  // points per call (4 doubles each: 2 MiB)
+static __device__ __align__(256) double scratch[4 * (size_t)PROBE_STATIC_MAX];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Resolves the device address of `scratch` on device `dev` (current).
+static hipError_t init_static_scratch(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = (double*)ptr;
+  return hipSuccess;
+}
+
+static double* static_scratch(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
 extern "C" {
 
 int32_t lbmdem_config_init(lbmdem_config* c) {
@@ -378,6 +412,10 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   dom->cfg = *cfg;
   dom->L = L;
   dom->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&dom->device) != hipSuccess || init_static_scratch(dom->device) != hipSuccess) {
+    delete dom;
+    return fail(nullptr, LBMDEM_EDEVICE, "device query or static scratch lookup failed");
+  }
   if (dev_buf) {
     dom->region = dev_buf;
   } else {
@@ -838,6 +876,21 @@ int32_t lbmdem_probe_density(lbmdem_domain* dom, int32_t n, const double* xyz, d
   HIPCHK(dom, hipGetLastError());
   HIPCHK(dom, hipMemcpyAsync(out, stage + 3 * (size_t)n, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
   HIPCHK(dom, hipStreamSynchronize(st));
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_probe_density_static(lbmdem_domain* dom, int32_t n, const double* xyz, double* out) {
+  if (!dom || n < 0 || (n > 0 && (!xyz || !out))) return LBMDEM_EINVAL;
+  if (n > PROBE_STATIC_MAX)
+    return fail(dom, LBMDEM_EINVAL, "too many probe points for the static scratch (at most 65536)");
+  if (n == 0) return LBMDEM_OK;
+  double* ptr = static_scratch(dom->device);
+  if (!ptr) return fail(dom, LBMDEM_EDEVICE, "static scratch not resolved on this device");
+  hipStream_t st = dom->stream;
+  HIPCHK(dom, hipMemcpyAsync(ptr, xyz, 24 * (size_t)n, hipMemcpyDeviceToDevice, st));
+  launch_probe_density(dom->d, ptr, n, st);
+  HIPCHK(dom, hipGetLastError());
+  HIPCHK(dom, hipMemcpyAsync(out, ptr + 3 * (size_t)n, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
   return LBMDEM_OK;
 }
 

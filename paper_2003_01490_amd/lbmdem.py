@@ -105,6 +105,7 @@ def lib():
         "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
         "lbmdem_sweep_bytes": (C.c_double, [vp]),
         "lbmdem_probe_density": (C.c_int32, [vp, C.c_int32, dp, dp]),
+        "lbmdem_probe_density_static": (C.c_int32, [vp, C.c_int32, vp, vp]),
         "lbmdem_device_copy": (C.c_int32, [vp, vp, C.c_size_t, vp]),
         "lbmdem_last_error": (C.c_char_p, [vp]),
     }
@@ -319,6 +320,15 @@ class Domain:
         out = np.empty(len(xyz))
         self._check(lib().lbmdem_probe_density(self.h, len(xyz), _dp(xyz), _dp(out)))
         return out
+
+    def probe_density_static(self, xyz, out):
+        """lbmdem_probe_density_static: ``xyz`` (n, 3) and ``out`` (n,) are
+        float64 device tensors; enqueued on the domain's stream, no wait."""
+        n = int(out.numel())
+        assert xyz.dtype == out.dtype and str(out.dtype) == "torch.float64" and xyz.numel() == 3 * n
+        assert xyz.is_cuda and out.is_cuda and xyz.is_contiguous() and out.is_contiguous()
+        self._check(lib().lbmdem_probe_density_static(self.h, n, C.c_void_p(xyz.data_ptr()),
+                                                      C.c_void_p(out.data_ptr())))
 
     def set_pdf(self, f):
         f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(19 * self.N))
