@@ -102,11 +102,16 @@ typedef struct lbmdem_config {
                                thread per sphere over a chain of launches
                                (binned neighbour search);
                                results are identical                              */
-  int32_t map_kernel;       /* boundary/commit pass: 0 automatic (one block per
-                               sphere from 128 spheres when it fits), 1 several
-                               blocks per sphere (box slabs and row chunks), 2
-                               one block per sphere (EINVAL if its LDS cube does
-                               not fit); the force sums differ in rounding order */
+  int32_t map_kernel;       /* particle-link boundary pass: 0 automatic (one
+                               block per sphere from 128 spheres when it fits),
+                               1 several blocks per sphere (box slabs and row
+                               chunks), 2 one block per sphere (EINVAL if its LDS
+                               cube does not fit), 3 fused: the boundary values
+                               and momentum exchange are formed inside the sweep
+                               and the mapping is updated geometrically; the DEM
+                               then runs after the sweep (EINVAL for max_radius
+                               below 1); the force sums differ in rounding
+                               order                                             */
   int32_t overlap;          /* 1 (default): inside a step, the one-workgroup DEM
                                kernels and the claims of the new positions run on
                                a second, library-owned stream beside the sweep

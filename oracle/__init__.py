@@ -73,6 +73,8 @@ def lib():
         L.ref_destroy.argtypes = [C.c_void_p]
         L.ref_add_sphere.restype = C.c_int32
         L.ref_add_sphere.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, C.c_double]
+        L.ref_add_spheres.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, dp, dp]
+        L.ref_add_spheres.restype = C.c_int32
         L.ref_set_mode.restype = C.c_int32
         L.ref_set_mode.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, C.c_double,
                                    C.c_double, C.c_double]
@@ -221,6 +223,18 @@ class RefDomain:
         if rc < 0:
             raise ValueError(f"oracle add_sphere failed: {rc}")
         return rc
+
+    def add_spheres(self, x, R, rho, u=None, w=None):
+        """n spheres at once (arrays (n, 3), (n,), (n,)), mapped once."""
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3))
+        n = len(x)
+        R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(n))
+        rho = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).reshape(n))
+        uu = np.ascontiguousarray(np.zeros((n, 3)) if u is None else np.asarray(u, dtype=np.float64).reshape(n, 3))
+        ww = np.ascontiguousarray(np.zeros((n, 3)) if w is None else np.asarray(w, dtype=np.float64).reshape(n, 3))
+        rc = lib().ref_add_spheres(self.h, n, _dp(x), _dp(uu), _dp(ww), _dp(R), _dp(rho))
+        if rc < 0:
+            raise ValueError(f"oracle add_spheres failed: {rc}")
 
     def try_add_sphere(self, x, R, rho, u=(0, 0, 0), w=(0, 0, 0)) -> int:
         return lib().ref_add_sphere(self.h, _dp(_vec(x)), _dp(_vec(u)), _dp(_vec(w)),

@@ -442,8 +442,10 @@ static double gap_ahead(const ref_domain* d, const sphere_t* s) {
 
 static void remap(ref_domain* d, int reconstruct);
 
-int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
-                       const double* w, double R, double rho) {
+/* inserts one sphere (checks of Sec. 2 set-up: inside the lattice, clear of
+ * the walls and of the other spheres) without re-mapping */
+static int32_t insert_sphere(ref_domain* d, const double* x, const double* u,
+                             const double* w, double R, double rho) {
   if (!d || !(R > 0.0) || !(rho > 0.0)) return -1;
   if (d->P >= d->cfg.max_spheres) return -6;
   for (int a = 0; a < 3; ++a)
@@ -469,8 +471,25 @@ int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
   int id = d->P;
   d->sp[id] = s;
   d->P += 1;
-  remap(d, 0);
   return id;
+}
+
+int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
+                       const double* w, double R, double rho) {
+  int32_t id = insert_sphere(d, x, u, w, R, rho);
+  if (id >= 0) remap(d, 0);
+  return id;
+}
+
+/* the same for n spheres (3n positions, velocities, angular velocities; NULL
+ * velocities read as zero), mapped once; the spheres before a failing one stay */
+int32_t ref_add_spheres(ref_domain* d, int32_t n, const double* x, const double* u,
+                        const double* w, const double* R, const double* rho) {
+  int32_t rc = 0;
+  for (int32_t k = 0; k < n && rc >= 0; ++k)
+    rc = insert_sphere(d, x + 3 * k, u ? u + 3 * k : NULL, w ? w + 3 * k : NULL, R[k], rho[k]);
+  remap(d, 0);
+  return rc < 0 ? rc : 0;
 }
 
 int32_t ref_set_mode(ref_domain* d, int32_t id, int32_t mode, const double* u_target,

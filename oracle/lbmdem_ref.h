@@ -96,6 +96,9 @@ int32_t ref_add_sphere(ref_domain* d, const double* x, const double* u,
 /* mode 0 free, 1 prescribed ramp (u = u_target (1 - exp(-c_acc t / t_st)),
  * released when the gap to the wall plane ahead along u_target drops below
  * release_gap), 2 fixed */
+/* n spheres at once, mapped once (0 or the first failure code) */
+int32_t ref_add_spheres(ref_domain* d, int32_t n, const double* x, const double* u,
+                        const double* w, const double* R, const double* rho);
 int32_t ref_set_mode(ref_domain* d, int32_t id, int32_t mode,
                      const double* u_target, double c_acc, double t_st,
                      double release_gap);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "liblbmdem.so")
-SOURCES = ["sweep.hip", "mapping.hip", "dem.hip", "fields.hip", "api.hip"]
+SOURCES = ["sweep.hip", "fused.hip", "mapping.hip", "dem.hip", "fields.hip", "api.hip"]
 OFFLOAD_ARCH = os.environ.get("LBMDEM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -54,20 +54,79 @@ bool ball_possible(const lbmdem_config& c) {
   return true;
 }
 
+// Fused step (map_kernel 3): tiles of the sweep, link boxes of the spheres
+// (2 ceil(R_max) + 6 cells per axis) and the slot arrays they index.
+struct FusedGeom {
+  int bx, by, gx, gy;
+  int E, snx, sny, snz;
+  bool ok;
+};
+
+FusedGeom fused_geom(const lbmdem_config& c) {
+  FusedGeom g{};
+  if (c.nx <= 256) {
+    g.bx = c.nx;
+    g.by = std::max(1, 256 / c.nx);
+  } else {
+    const int cand[4] = {128, 256, 192, 64};
+    g.bx = 256;
+    for (int v : cand)
+      if (c.nx % v == 0) {
+        g.bx = v;
+        break;
+      }
+    g.by = 256 / g.bx;
+  }
+  g.gx = (c.nx + g.bx - 1) / g.bx;
+  g.gy = (c.ny + g.by - 1) / g.by;
+  g.E = 2 * (int)std::ceil(std::max(c.max_radius, 0.0)) + 6;
+  g.ok = c.max_spheres > 0 && c.max_radius >= 1.0 && c.max_radius <= 1000.0;
+  // tiles a link box can meet along one axis (one more on a periodic axis,
+  // where the wrap may pass a shorter last tile); distinct tiles take
+  // distinct slots since a tile's slot is its index relative to the box's
+  // first tile modulo the tile count, and a slot beyond these is reported
+  auto axis = [&](int n, int b, int tiles, int wall) {
+    (void)n;
+    return std::min((g.E + b - 1) / b + (wall ? 1 : 2), tiles);
+  };
+  g.snx = axis(c.nx, g.bx, g.gx, c.walls[0]);
+  g.sny = axis(c.ny, g.by, g.gy, c.walls[1]);
+  g.snz = axis(c.nz, 1, c.nz, c.walls[2]);
+  return g;
+}
+
+// bins of the geometric mapping: edge >= R_max + max(delta_aB, 1) + 1
+void mbin_dims(const lbmdem_config& c, int* nb) {
+  const int n[3] = {c.nx, c.ny, c.nz};
+  double h = c.max_radius + std::max(c.delta_ab, 1.0) + 1.0;
+  for (;;) {
+    double tot = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      nb[a] = std::max(1, (int)std::floor((double)n[a] / h));
+      tot *= nb[a];
+    }
+    if (tot <= 4.0e6) return;
+    h *= 1.25;
+  }
+}
+
+// the fused step is chosen explicitly (map_kernel 3)
+bool use_fused(const lbmdem_config& c) { return c.map_kernel == 3; }
+
 bool use_ball(const lbmdem_config& c) {
-  if (c.map_kernel == 1) return false;
+  if (c.map_kernel == 1 || use_fused(c)) return false;
   if (c.map_kernel == 2) return true;
   return c.max_spheres >= BALL_MIN_SPHERES && ball_possible(c);
 }
 
 int zblocks(const lbmdem_config& c) {
-  if (use_ball(c)) return 1;
+  if (use_ball(c) || use_fused(c)) return 1;
   const int per = (MAP_BLOCKS_TARGET + std::max(c.max_spheres, 1) - 1) / std::max(c.max_spheres, 1);
   return std::max(1, std::min(std::min(c.nz, box_extent(c)), per));
 }
 
 int rowblocks(const lbmdem_config& c) {
-  if (use_ball(c)) return 1;
+  if (use_ball(c) || use_fused(c)) return 1;
   const int e = std::min(c.ny, box_extent(c));
   const int full = std::max(1, (e + COMMIT_ROWS - 1) / COMMIT_ROWS);
   const long long have = (long long)std::max(c.max_spheres, 1) * zblocks(c);
@@ -96,7 +155,7 @@ void bin_dims(const lbmdem_config& c, int* nb) {
 }
 
 struct Layout {
-  size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage;
+  size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage, slot, slot_stamp, mbins;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
       old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, order, bins, ctl, partial, status;
   size_t total;
@@ -120,6 +179,17 @@ Layout make_layout(const lbmdem_config& c) {
   L.claim = take(8 * N);
   L.shellstamp = take(4 * N);
   L.stage = take(8 * N);
+  // fused step only (transient, so not part of a checkpoint)
+  {
+    const bool f = use_fused(c);
+    const FusedGeom g = fused_geom(c);
+    const size_t per = f ? (size_t)g.snx * g.sny * g.snz : 0;
+    int mb[3] = {1, 1, 1};
+    if (f) mbin_dims(c, mb);
+    L.slot = take(48 * P * per);
+    L.slot_stamp = take(4 * P * per);
+    L.mbins = take(f ? 4 * (size_t)mb[0] * mb[1] * mb[2] * (1 + BIN_CAP) : 0);
+  }
   L.x = take(24 * P);
   L.u = take(24 * P);
   L.w = take(24 * P);
@@ -179,10 +249,12 @@ const char* check_config(const lbmdem_config* c) {
   if (!(c->friction >= 0.0)) return "friction must be non-negative";
   if (!(c->cut_n > 0.0 && c->cut_tt > 0.0 && c->cut_tr > 0.0)) return "cut-offs must be positive";
   if (c->dem_kernel < 0 || c->dem_kernel > 2) return "dem_kernel must be 0..2";
-  if (c->map_kernel < 0 || c->map_kernel > 2) return "map_kernel must be 0..2";
+  if (c->map_kernel < 0 || c->map_kernel > 3) return "map_kernel must be 0..3";
   if (c->overlap != 0 && c->overlap != 1) return "overlap must be 0 or 1";
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(c->body_force[a])) return "body_force must be finite";
+  if (c->map_kernel == 3 && !fused_geom(*c).ok)
+    return "map_kernel 3 needs a sphere radius of at least 1";
   if (c->map_kernel == 2 && !ball_possible(*c))
     return "map_kernel 2 needs the staged cube (R_max + 4 cells each side) within 60000 bytes of LDS and "
            "within every periodic extent";
@@ -321,6 +393,11 @@ static int32_t refresh_order(lbmdem_domain* dom) {
 
 static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
   dom->d.P = (int)dom->hR.size();
+  if (dom->d.fused) {
+    timed(dom, 2, dom->stream, [&] { launch_mapping_fused(dom->d, reconstruct, dom->stream); });
+    HIPCHK(dom, hipGetLastError());
+    return LBMDEM_OK;
+  }
   if (int32_t rc = refresh_order(dom)) return rc;
   timed(dom, 2, dom->stream, [&] { launch_mapping(dom->d, reconstruct, dom->stream); });
   HIPCHK(dom, hipGetLastError());
@@ -501,6 +578,25 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.stage_edge = stage_edge(*cfg);
   d.list_cap = list_cap(*cfg);
   d.partial = (double*)(base + L.partial);
+  d.fused = use_fused(*cfg) ? 1 : 0;
+  {
+    const FusedGeom g = fused_geom(*cfg);
+    d.fbx = g.bx;
+    d.fby = g.by;
+    d.fgx = g.gx;
+    d.fgy = g.gy;
+    d.sl_E = g.E;
+    d.sl_nx = g.snx;
+    d.sl_ny = g.sny;
+    d.sl_nz = g.snz;
+    d.sl_per = d.fused ? g.snx * g.sny * g.snz : 0;
+    d.slot = (double*)(base + L.slot);
+    d.slot_stamp = (uint32_t*)(base + L.slot_stamp);
+    if (d.fused) mbin_dims(*cfg, d.mbins.n);
+    else d.mbins.n[0] = d.mbins.n[1] = d.mbins.n[2] = 1;
+    d.mbins.cell = (int*)(base + L.mbins);
+    d.stage32 = (uint32_t*)(base + L.stage);
+  }
   d.status = (int*)(base + L.status);
   d.n_sub = cfg->n_sub;
   d.force_averaging = cfg->force_averaging;
@@ -520,7 +616,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
 
   // particle block and status are plain zeros except the free history slots
   int32_t rc = LBMDEM_OK;
-  if (hipMemsetAsync(base + L.x, 0, L.total - L.x, s) != hipSuccess ||
+  if (hipMemsetAsync(base + L.slot, 0, L.total - L.slot, s) != hipSuccess ||
       hipMemsetD32Async((hipDeviceptr_t)(base + L.hist_id), (int)0x80000000, Pm * HIST_SLOTS, s) !=
           hipSuccess)
     rc = fail(nullptr, LBMDEM_EDEVICE, "initialising the particle block failed");
@@ -728,6 +824,27 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
   if (dom->batch) return fail(dom, LBMDEM_EINVAL, "domain is stepped by its batch");
   dom->d.P = (int)dom->hR.size();
+  hipStream_t s0 = dom->stream;
+  if (dom->d.fused) {
+    // Alg. 1 in order on one stream: the sweep with the link boundary values
+    // and momentum exchange, the per-sphere sums, the DEM sub-cycles, then the
+    // mapping update with reconstruction and the step control
+    for (int k = 0; k < nsteps; ++k) {
+      hipError_t e = hipSuccess;
+      timed(dom, 0, s0, [&] { launch_sweep_fused(dom->d, s0); });
+      timed(dom, 1, s0, [&] {
+        launch_force_reduce(dom->d, s0);
+        e = launch_dem(dom->d, dom->cfg.dem_kernel, !dom->may_prescribe, s0);
+      });
+      if (e != hipSuccess) {
+        dom->failed = 1;
+        return fail(dom, LBMDEM_EDEVICE, std::string("DEM launch failed: ") + hipGetErrorString(e));
+      }
+      timed(dom, 2, s0, [&] { launch_update_fused(dom->d, s0); });
+    }
+    HIPCHK(dom, hipGetLastError());
+    return LBMDEM_OK;
+  }
   const bool ov = overlap_step(dom);
   if (ov && nsteps > 0)
     if (int32_t rc = ensure_side(dom)) return rc;
@@ -796,9 +913,11 @@ int32_t lbmdem_sync(lbmdem_domain* dom) {
     dom->failed = 1;
     return fail(dom, LBMDEM_EUNSTABLE, "non-finite particle state");
   }
-  if (st & (ST_HIST_FULL | ST_NBR_FULL)) {
+  if (st & (ST_HIST_FULL | ST_NBR_FULL | ST_TILE_FULL)) {
     dom->failed = 1;
-    return fail(dom, LBMDEM_ECAPACITY, "contact-history, neighbour-list or bin slots exhausted");
+    return fail(dom, LBMDEM_ECAPACITY,
+                (st & ST_TILE_FULL) ? "a sweep tile met more spheres than its table holds"
+                                    : "contact-history, neighbour-list or bin slots exhausted");
   }
   return dom->failed ? LBMDEM_ESTATE : LBMDEM_OK;
 }
@@ -950,6 +1069,7 @@ int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f) {
     HIPCHK(dom, hipGetLastError());
     HIPCHK(dom, hipStreamSynchronize(st));
   }
+  if (dom->d.fused) return LBMDEM_OK;  // links are formed by the next sweep
   if (int32_t rc = pin_mapped_positions(dom)) return rc;
   return remap(dom, false);
 }
@@ -1317,7 +1437,8 @@ int32_t lbmdem_batch_admit(lbmdem_batch* b, lbmdem_domain* dom, int32_t* slot) {
   if (dom->stream != b->stream) return bfail(b, LBMDEM_EINVAL, "domain was created on another stream");
   if (b->storage >= 0 && dom->cfg.storage != b->storage)
     return bfail(b, LBMDEM_EINVAL, "all domains of a batch share one storage precision");
-  if (dom->d.map_ball) return bfail(b, LBMDEM_EINVAL, "batched domains use the slab boundary pass (map_kernel 1)");
+  if (dom->d.map_ball || dom->d.fused)
+    return bfail(b, LBMDEM_EINVAL, "batched domains use the slab boundary pass (map_kernel 1)");
   const size_t fp = dom->L.total;
   if (b->used + fp > b->pool) return bfail(b, LBMDEM_ENOMEM, "pool budget exceeded");
   b->storage = dom->cfg.storage;

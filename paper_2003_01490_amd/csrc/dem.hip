@@ -616,24 +616,6 @@ __device__ __forceinline__ void bin_insert(const DevDomain& d, const DevParticle
     atomicOr(d.status, ST_NBR_FULL);
 }
 
-// Bins along one axis that can hold partners of a sphere in bin b: the three
-// around it (wrapped on periodic axes), or every bin when there are fewer than
-// three.  Entry e of axis_count(nb) entries; false if it lies beyond a wall.
-__device__ __forceinline__ int axis_count(int nb) { return nb < 3 ? nb : 3; }
-__device__ __forceinline__ bool axis_bin(int b, int nb, bool wall, int e, int* k) {
-  if (nb < 3) {
-    *k = e;
-    return true;
-  }
-  int v = b + e - 1;
-  if (v < 0 || v >= nb) {
-    if (wall) return false;
-    v = v < 0 ? v + nb : v - nb;
-  }
-  *k = v;
-  return true;
-}
-
 // the neighbour test of dem_body over the candidates of the surrounding bins,
 // kept sorted by id, so both kernels produce the same list
 __device__ __forceinline__ void binned_neighbours(const DevDomain& d, const DevParticles& p, int i) {

@@ -39,6 +39,7 @@ constexpr int MODE_FIXED = 2;
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_HIST_FULL = 2;
 constexpr int ST_NBR_FULL = 4;
+constexpr int ST_TILE_FULL = 8;   // a fused-sweep tile met more spheres than its table holds
 
 constexpr int BIN_CAP = 15;      // sphere ids per neighbour-search bin (+1 count)
 
@@ -152,6 +153,20 @@ struct DevDomain {
   double nu;
   double skin;     // neighbour-list skin
   DevBins bins;
+  // Fused step: the particle links are formed inside the sweep (tiles of
+  // fbx x fby cells, fgx x fgy tiles per plane); each tile leaves one
+  // momentum-exchange partial per sphere it touches in that sphere's slot
+  // array (slots indexed by the tile's position in the sphere's link box of
+  // sl_E cells per axis: sl_nx x sl_ny x sl_nz tiles), stamped with the step.
+  // Mapping updates find the spheres around a cell through the mapping bins
+  // (edge >= R_max + max(delta_aB, 1) + 1).
+  int fused;
+  int fbx, fby, fgx, fgy;
+  int sl_E, sl_nx, sl_ny, sl_nz, sl_per;
+  double* slot;          // [P][sl_per][6]
+  uint32_t* slot_stamp;  // [P][sl_per]
+  DevBins mbins;
+  uint32_t* stage32;     // [N] cell states of a full mapping update (in the stage buffer)
 };
 
 __host__ __device__ inline long long cidx(const DevDomain& d, int i, int j, int k) {
@@ -172,6 +187,53 @@ __device__ inline double min_image(double v, int n, int wall) {
   if (v > 0.5 * L) return v - L;
   if (v < -0.5 * L) return v + L;
   return v;
+}
+
+// i mod n for i that is almost always within one period of [0, n): one
+// conditional wrap, the full modulo only when that does not land in range
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  if (i < 0)
+    i += n;
+  else if (i >= n)
+    i -= n;
+  return (unsigned)i < (unsigned)n ? i : wrapmod(i, n);
+}
+
+__device__ inline double cell_d2(const DevDomain& d, int i, int j, int k, const double* xp) {
+#pragma clang fp contract(off)
+  const double dx = min_image(((double)i + 0.5) - xp[0], d.nx, d.walls[0]);
+  const double dy = min_image(((double)j + 0.5) - xp[1], d.ny, d.walls[1]);
+  const double dz = min_image(((double)k + 0.5) - xp[2], d.nz, d.walls[2]);
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// smallest root in [0,1] of |r + delta c|^2 = R^2 (x_b = x + delta_q c_q)
+__device__ inline double link_delta(const double* r, const int* c, double R) {
+  const double cc = (double)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  const double b = r[0] * c[0] + r[1] * c[1] + r[2] * c[2];
+  const double e = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) - R * R;
+  double disc = b * b - cc * e;
+  if (disc < 0.0) disc = 0.0;
+  double dl = (-b - sqrt(disc)) / cc;
+  return dl < 0.0 ? 0.0 : (dl > 1.0 ? 1.0 : dl);
+}
+
+// Bins along one axis that can hold partners of a sphere in bin b: the three
+// around it (wrapped on periodic axes), or every bin when there are fewer than
+// three.  Entry e of axis_count(nb) entries; false if it lies beyond a wall.
+__device__ __forceinline__ int axis_count(int nb) { return nb < 3 ? nb : 3; }
+__device__ __forceinline__ bool axis_bin(int b, int nb, bool wall, int e, int* k) {
+  if (nb < 3) {
+    *k = e;
+    return true;
+  }
+  int v = b + e - 1;
+  if (v < 0 || v >= nb) {
+    if (wall) return false;
+    v = v < 0 ? v + nb : v - nb;
+  }
+  *k = v;
+  return true;
 }
 
 // Device tables of a batch of domains (one launch per kernel for all of them):
@@ -301,5 +363,14 @@ void launch_dem_batch(const BatchTables& b, hipStream_t s);
 void launch_claim_batch(const BatchTables& b, hipStream_t s);
 void launch_update_batch(const BatchTables& b, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// fused step: the sweep with the particle links and momentum exchange, and
+// the per-sphere sums of its tile partials (into partial[i][6])
+void launch_sweep_fused(const DevDomain& d, hipStream_t s);
+void launch_force_reduce(const DevDomain& d, hipStream_t s);
+// fused step after the DEM: mapping bins of the new positions, reconstruction,
+// flags and owners of the cells that change, step control
+void launch_update_fused(const DevDomain& d, hipStream_t s);
+// mapping of the current positions outside a step (every cell evaluated)
+void launch_mapping_fused(const DevDomain& d, bool reconstruct, hipStream_t s);
 
 }  // namespace lbmdem

@@ -107,24 +107,6 @@ __device__ inline void mapped_ball_box(const DevDomain& d, int i, Box& b) {
   }
 }
 
-// i mod n for i that is almost always within one period of [0, n): one
-// conditional wrap, the full modulo only when that does not land in range
-__device__ __forceinline__ int wrap_near(int i, int n) {
-  if (i < 0)
-    i += n;
-  else if (i >= n)
-    i -= n;
-  return (unsigned)i < (unsigned)n ? i : wrapmod(i, n);
-}
-
-__device__ inline double cell_d2(const DevDomain& d, int i, int j, int k, const double* xp) {
-#pragma clang fp contract(off)
-  const double dx = min_image(((double)i + 0.5) - xp[0], d.nx, d.walls[0]);
-  const double dy = min_image(((double)j + 0.5) - xp[1], d.ny, d.walls[1]);
-  const double dz = min_image(((double)k + 0.5) - xp[2], d.nz, d.walls[2]);
-  return (dx * dx + dy * dy) + dz * dz;
-}
-
 // state of a cell after the current mapping update (claims of this stamp);
 // the three loads are independent so that they are in flight together
 __device__ inline int new_state(const DevDomain& d, long long c, uint32_t stamp, int* own) {
@@ -252,17 +234,18 @@ __global__ __launch_bounds__(256) void k_claim(DevDomain d, int in_step, int lis
 __global__ void k_new_stamp(DevCtl* ctl) { ctl->stamp += 1; }
 
 // Eq. (PDF_reconstruction) for cell (ii,jj,kk) formerly covered by sphere i
-template <typename T>
-__device__ void reconstruct(const DevDomain& d, T* buf, uint32_t stamp, int ii, int jj, int kk,
-                            int i) {
+// (one thread; `usable(y, i, j, k)` says whether neighbour y at (i, j, k) is
+// fluid before and after the mapping update)
+template <typename T, typename V>
+__device__ void reconstruct_with(const DevDomain& d, T* buf, int ii, int jj, int kk, int i, V usable) {
   const size_t N = (size_t)d.N;
   const long long c = cidx(d, ii, jj, kk);
   double rsum = 0.0;
   int nvalid = 0;
   for (int q = 1; q < Q; ++q) {
-    const long long y = cidx(d, wrapi(ii + CX[q], d.nx), wrapi(jj + CY[q], d.ny), wrapi(kk + CZ[q], d.nz));
-    int o;
-    if ((d.flags[y] & (F_SOLID | F_WALL)) || !is_fluid_state(new_state(d, y, stamp, &o))) continue;
+    const int yi = wrapi(ii + CX[q], d.nx), yj = wrapi(jj + CY[q], d.ny), yk = wrapi(kk + CZ[q], d.nz);
+    const long long y = cidx(d, yi, yj, yk);
+    if (!usable(y, yi, yj, yk)) continue;
     double r = 0.0;
     for (int p = 0; p < Q; ++p) r += ldv<T>(buf + (size_t)p * N + y) + WQ[p];
     rsum += r;
@@ -284,11 +267,12 @@ __device__ void reconstruct(const DevDomain& d, T* buf, uint32_t stamp, int ii, 
   const int axp[3] = {4, 1, 5}, axm[3] = {3, 2, 6};
   for (int bb = 0; bb < 3; ++bb) {
     const int qp = axp[bb], qm = axm[bb];
-    const long long yp = cidx(d, wrapi(ii + CX[qp], d.nx), wrapi(jj + CY[qp], d.ny), wrapi(kk + CZ[qp], d.nz));
-    const long long ym = cidx(d, wrapi(ii + CX[qm], d.nx), wrapi(jj + CY[qm], d.ny), wrapi(kk + CZ[qm], d.nz));
-    int o;
-    const bool vp = !(d.flags[yp] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, yp, stamp, &o));
-    const bool vm = !(d.flags[ym] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, ym, stamp, &o));
+    const int pi = wrapi(ii + CX[qp], d.nx), pj = wrapi(jj + CY[qp], d.ny), pk = wrapi(kk + CZ[qp], d.nz);
+    const int mi = wrapi(ii + CX[qm], d.nx), mj = wrapi(jj + CY[qm], d.ny), mk = wrapi(kk + CZ[qm], d.nz);
+    const long long yp = cidx(d, pi, pj, pk);
+    const long long ym = cidx(d, mi, mj, mk);
+    const bool vp = usable(yp, pi, pj, pk);
+    const bool vm = usable(ym, mi, mj, mk);
     double up[3] = {0, 0, 0}, um[3] = {0, 0, 0};
     for (int p = 0; p < Q; ++p) {
       const double fp = ldv<T>(buf + (size_t)p * N + yp) + WQ[p];
@@ -327,21 +311,30 @@ __device__ void reconstruct(const DevDomain& d, T* buf, uint32_t stamp, int ii, 
   }
 }
 
+template <typename T>
+__device__ void reconstruct(const DevDomain& d, T* buf, uint32_t stamp, int ii, int jj, int kk, int i) {
+  reconstruct_with<T>(d, buf, ii, jj, kk, i, [&](long long y, int, int, int) {
+    int o;
+    return !(d.flags[y] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, y, stamp, &o));
+  });
+}
+
 // Eq. (PDF_reconstruction) for cell c formerly covered by sphere i, computed
 // by one wavefront: lane q (1..18) checks neighbour x + c_q and forms its
 // density and velocity from 19 independent loads; the lanes' values are then
 // combined in q order (the same order as a serial loop) and lane q writes f_q.
-template <typename T>
-__device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, long long c, int i,
-                                 int lane) {
+// The same for any rule `usable(y, i, j, k)` that says whether neighbour y
+// (at (i, j, k)) is fluid before and after the mapping update.
+template <typename T, typename V>
+__device__ void reconstruct_wave_with(const DevDomain& d, T* buf, long long c, int i, int lane, V usable) {
   const size_t N = (size_t)d.N;
   const int ii = (int)(c % d.nx), jj = (int)((c / d.nx) % d.ny), kk = (int)(c / ((long long)d.nx * d.ny));
   bool valid = false;
   double rn = 0.0, un[3] = {0.0, 0.0, 0.0};
   if (lane >= 1 && lane < Q) {
-    const long long y = cidx(d, wrapi(ii + CX[lane], d.nx), wrapi(jj + CY[lane], d.ny), wrapi(kk + CZ[lane], d.nz));
-    int o;
-    valid = !(d.flags[y] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, y, stamp, &o));
+    const int yi = wrapi(ii + CX[lane], d.nx), yj = wrapi(jj + CY[lane], d.ny), yk = wrapi(kk + CZ[lane], d.nz);
+    const long long y = cidx(d, yi, yj, yk);
+    valid = usable(y, yi, yj, yk);
     if (valid) {
       double f[Q];
 #pragma unroll
@@ -416,6 +409,14 @@ __device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, lon
   }
 }
 
+template <typename T>
+__device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, long long c, int i, int lane) {
+  reconstruct_wave_with<T>(d, buf, c, i, lane, [&](long long y, int, int, int) {
+    int o;
+    return !(d.flags[y] & (F_SOLID | F_WALL)) && is_fluid_state(new_state(d, y, stamp, &o));
+  });
+}
+
 constexpr int RECON_LIST = 1024;
 
 template <typename T>
@@ -466,17 +467,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_recon(DevDomain d, int in_step) {
   if (!map_live(d.ctl, in_step)) return;
   recon_block<T>(d, blockIdx.x, map_buffer(d.ctl, in_step), map_stamp(d.ctl));
-}
-
-// smallest root in [0,1] of |r + delta c|^2 = R^2 (x_b = x + delta_q c_q)
-__device__ inline double link_delta(const double* r, const int* c, double R) {
-  const double cc = (double)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-  const double b = r[0] * c[0] + r[1] * c[1] + r[2] * c[2];
-  const double e = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) - R * R;
-  double disc = b * b - cc * e;
-  if (disc < 0.0) disc = 0.0;
-  double dl = (-b - sqrt(disc)) / cc;
-  return dl < 0.0 ? 0.0 : (dl > 1.0 ? 1.0 : dl);
 }
 
 template <typename T>
@@ -1164,6 +1154,277 @@ void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
   launch_claim(d, 0, false, s);
   launch_update(d, reconstruct, 0, s);
   hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
+}
+
+// ---- geometric mapping of the fused step ------------------------------------
+// With the particle links formed in the sweep, the mapping update needs the
+// flags and owners of the new positions and the reconstruction of uncovered
+// cells only.  Both follow from the positions alone: the state of a cell is
+// solid of the lowest id whose closed ball holds its centre, else shell within
+// R + delta_aB of some sphere, else fluid (walls never change) -- evaluated
+// from the spheres listed in the 27 mapping bins around the cell (every sphere
+// whose shell ball can hold the centre is among them, the bin edge being at
+// least R_max + delta_aB + 1).  Inside a step each sphere visits the cells of
+// its old and new shell boxes and rewrites only those where its own solid or
+// shell membership changed: a cell whose state changes has some sphere whose
+// membership changed, and every sphere that rewrites a cell writes the same
+// value.  Outside a step (new, moved or restored spheres) every cell is
+// evaluated.
+
+__device__ __forceinline__ int mbin_index(const DevDomain& d, const double* x, int* b) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int nb = d.mbins.n[a];
+    const int k = (int)floor(x[a] * (double)nb / (double)n[a]);
+    b[a] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
+  }
+  return b[0] + d.mbins.n[0] * (b[1] + d.mbins.n[1] * b[2]);
+}
+
+// insert (clear = 0) or remove (clear = 1: zero the count of its bin) every
+// sphere by its current position
+__global__ void k_mbins(DevDomain d, int in_step, int clear) {
+  if (in_step ? !step_live(d.ctl) : d.ctl->frozen) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.P) return;
+  const double* x = d.p.x + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    atomicOr(d.status, ST_NONFINITE);
+    return;
+  }
+  int b[3];
+  int* c = d.mbins.cell + (size_t)mbin_index(d, x, b) * (1 + BIN_CAP);
+  if (clear) {
+    c[0] = 0;
+    return;
+  }
+  const int k = atomicAdd(c, 1);
+  if (k < BIN_CAP)
+    c[1 + k] = i;
+  else
+    atomicOr(d.status, ST_NBR_FULL);
+}
+
+// state of non-wall cell (i, j, k) at the current positions (S_FLUID,
+// S_SHELL or S_SOLID with *own the lowest id)
+__device__ inline int geo_state(const DevDomain& d, int i, int j, int k, int* own) {
+  const double xc[3] = {(double)i + 0.5, (double)j + 0.5, (double)k + 0.5};
+  int b[3];
+  mbin_index(d, xc, b);
+  const int n0 = d.mbins.n[0], n1 = d.mbins.n[1], n2 = d.mbins.n[2];
+  int best = 0x7FFFFFFF;
+  bool shell = false;
+  for (int ez = 0; ez < axis_count(n2); ++ez) {
+    int kz;
+    if (!axis_bin(b[2], n2, d.walls[2], ez, &kz)) continue;
+    for (int ey = 0; ey < axis_count(n1); ++ey) {
+      int ky;
+      if (!axis_bin(b[1], n1, d.walls[1], ey, &ky)) continue;
+      for (int ex = 0; ex < axis_count(n0); ++ex) {
+        int kx;
+        if (!axis_bin(b[0], n0, d.walls[0], ex, &kx)) continue;
+        const int* c = d.mbins.cell + (size_t)(kx + n0 * (ky + n1 * kz)) * (1 + BIN_CAP);
+        const int m = min(c[0], BIN_CAP);
+        for (int e = 0; e < m; ++e) {
+          const int s = c[1 + e];
+          double R2, rs2;
+          {
+#pragma clang fp contract(off)
+            const double R = d.p.R[s];
+            const double rs = R + d.delta_ab;
+            R2 = R * R;
+            rs2 = rs * rs;
+          }
+          const double d2 = cell_d2(d, i, j, k, d.p.x + 3 * s);
+          if (d2 <= R2 && s < best) best = s;
+          if (d2 <= rs2) shell = true;
+        }
+      }
+    }
+  }
+  *own = best;
+  return best != 0x7FFFFFFF ? S_SOLID : (shell ? S_SHELL : S_FLUID);
+}
+
+__device__ __forceinline__ bool wall_cell(const DevDomain& d, int i, int j, int k) {
+  return (d.walls[0] && (i == 0 || i == d.nx - 1)) || (d.walls[1] && (j == 0 || j == d.ny - 1)) ||
+         (d.walls[2] && (k == 0 || k == d.nz - 1));
+}
+
+// Reconstruction inside a step (one block per sphere i): cells of i's solid
+// at the mapped positions (flags and owners in place) that are not solid at
+// the new positions, from neighbours fluid before (flags) and after
+// (geo_state); written into the buffer the sweep has just filled.
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon_geo(DevDomain d) {
+  if (!step_live(d.ctl)) return;
+  const int i = blockIdx.x;
+  if (i >= d.P) return;
+  T* buf = (T*)d.pdf[map_buffer(d.ctl, 1)];
+  __shared__ long long cand[RECON_LIST];
+  __shared__ int ncand;
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  Box bx;
+  mapped_ball_box(d, i, bx);
+  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
+  const double xn[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
+  double R2;
+  {
+#pragma clang fp contract(off)
+    const double R = d.p.R[i];
+    R2 = R * R;
+  }
+  auto usable = [&](long long y, int yi, int yj, int yk) {
+    int o;
+    return !(d.flags[y] & (F_SOLID | F_WALL)) && geo_state(d, yi, yj, yk, &o) != S_SOLID;
+  };
+  FOR_BOX_CELLS(d, bx, 0, 1, {
+    if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
+      const long long c = cidx(d, ii, jj, kk);
+      int o;
+      if ((d.flags[c] & F_SOLID) && d.owner[c] == i && geo_state(d, ii, jj, kk, &o) != S_SOLID) {
+        const int k = atomicAdd(&ncand, 1);
+        if (k < RECON_LIST)
+          cand[k] = c;
+        else
+          reconstruct_with<T>(d, buf, ii, jj, kk, i, usable);  // list full: rebuild here
+      }
+    }
+  })
+  __syncthreads();
+  const int n = min(ncand, RECON_LIST);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  for (int e = wave; e < n; e += nwave) reconstruct_wave_with<T>(d, buf, cand[e], i, lane, usable);
+}
+
+// Flags and owners inside a step (one block per sphere i): the cells of the
+// old and new shell boxes where i's solid or shell membership changed get the
+// state of the new positions.
+__global__ __launch_bounds__(256) void k_remap_geo(DevDomain d) {
+  if (!step_live(d.ctl)) return;
+  const int i = blockIdx.x;
+  if (i >= d.P) return;
+  Box bx;
+  sphere_box(d, i, true, bx);
+  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
+  const double xn[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
+  double R2, rs2;
+  {
+#pragma clang fp contract(off)
+    const double R = d.p.R[i];
+    const double rs = R + d.delta_ab;
+    R2 = R * R;
+    rs2 = rs * rs;
+  }
+  FOR_BOX_CELLS(d, bx, 0, 1, {
+    if (!wall_cell(d, ii, jj, kk)) {
+      const double d2o = cell_d2(d, ii, jj, kk, xo), d2n = cell_d2(d, ii, jj, kk, xn);
+      if ((d2o <= R2) != (d2n <= R2) || (d2o <= rs2) != (d2n <= rs2)) {
+        int own;
+        const int st = geo_state(d, ii, jj, kk, &own);
+        const long long c = cidx(d, ii, jj, kk);
+        d.flags[c] = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+        if (st == S_SOLID) d.owner[c] = own;
+      }
+    }
+  })
+}
+
+// End of a fused step: the mapping bins are emptied (by the positions they
+// were filled with) and one thread runs the step control.
+__global__ void k_advance_fused(DevDomain d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.P) {
+    const double* x = d.p.x + 3 * i;
+    if (isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2])) {
+      int b[3];
+      d.mbins.cell[(size_t)mbin_index(d, x, b) * (1 + BIN_CAP)] = 0;
+    }
+  }
+  if (i == 0) step_control(d);
+}
+
+// Outside a step: the state of every cell at the current positions into the
+// stage (2 bits of state, owner + 1 above them), reconstruction of cells that
+// leave a solid, then the commit.
+__global__ void k_geo_stage(DevDomain d) {
+  if (d.ctl->frozen) return;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < (size_t)d.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % d.nx), j = (int)((c / d.nx) % d.ny), k = (int)(c / ((size_t)d.nx * d.ny));
+    if (wall_cell(d, i, j, k)) {
+      d.stage32[c] = (uint32_t)S_WALL;
+      continue;
+    }
+    int own;
+    const int st = geo_state(d, i, j, k, &own);
+    d.stage32[c] = (uint32_t)st | (st == S_SOLID ? ((uint32_t)(own + 1) << 2) : 0u);
+  }
+}
+
+template <typename T>
+__global__ void k_recon_full(DevDomain d) {
+  if (d.ctl->frozen) return;
+  T* buf = (T*)d.pdf[map_buffer(d.ctl, 0)];
+  auto usable = [&](long long y, int, int, int) {
+    return !(d.flags[y] & (F_SOLID | F_WALL)) && (d.stage32[y] & 3u) <= (uint32_t)S_SHELL;
+  };
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < (size_t)d.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    if (!(d.flags[c] & F_SOLID) || (d.stage32[c] & 3u) > (uint32_t)S_SHELL) continue;
+    const int i = (int)(c % d.nx), j = (int)((c / d.nx) % d.ny), k = (int)(c / ((size_t)d.nx * d.ny));
+    reconstruct_with<T>(d, buf, i, j, k, d.owner[c], usable);
+  }
+}
+
+__global__ void k_commit_full(DevDomain d) {
+  if (d.ctl->frozen) return;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < (size_t)d.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t v = d.stage32[c];
+    const int st = (int)(v & 3u);
+    if (st == S_WALL) continue;
+    d.flags[c] = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+    if (st == S_SOLID) d.owner[c] = (int)(v >> 2) - 1;
+  }
+}
+
+static dim3 cells_grid(long long N) {
+  long long b = (N + 255) / 256;
+  return dim3((unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b)));
+}
+
+void launch_mapping_fused(const DevDomain& d, bool reconstruct, hipStream_t s) {
+  const dim3 gp((unsigned)((d.P + 255) / 256 > 0 ? (d.P + 255) / 256 : 1));
+  if (d.P > 0) hipLaunchKernelGGL(k_mbins, gp, dim3(256), 0, s, d, 0, 0);
+  hipLaunchKernelGGL(k_geo_stage, cells_grid(d.N), dim3(256), 0, s, d);
+  if (reconstruct) {
+    if (d.storage == 0)
+      hipLaunchKernelGGL(k_recon_full<double>, cells_grid(d.N), dim3(256), 0, s, d);
+    else if (d.storage == 1)
+      hipLaunchKernelGGL(k_recon_full<float>, cells_grid(d.N), dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(k_recon_full<__half>, cells_grid(d.N), dim3(256), 0, s, d);
+  }
+  hipLaunchKernelGGL(k_commit_full, cells_grid(d.N), dim3(256), 0, s, d);
+  if (d.P > 0) hipLaunchKernelGGL(k_mbins, gp, dim3(256), 0, s, d, 0, 1);
+}
+
+void launch_update_fused(const DevDomain& d, hipStream_t s) {
+  const unsigned gp = (unsigned)((d.P + 255) / 256 > 0 ? (d.P + 255) / 256 : 1);
+  if (d.P > 0) {
+    hipLaunchKernelGGL(k_mbins, dim3(gp), dim3(256), 0, s, d, 1, 0);
+    if (d.storage == 0)
+      hipLaunchKernelGGL(k_recon_geo<double>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+    else if (d.storage == 1)
+      hipLaunchKernelGGL(k_recon_geo<float>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(k_recon_geo<__half>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(256), 0, s, d);
+  }
+  hipLaunchKernelGGL(k_advance_fused, dim3(gp), dim3(256), 0, s, d);
 }
 
 // ---- batched mapping update (slab blocks; one launch per kernel for all domains)

@@ -15,8 +15,8 @@ def oracle_domain(wl: W.Workload, **over):
     p.update(over)
     p = {k: v for k, v in p.items() if k in ORACLE_KEYS}
     d = O.RefDomain(O.make_config(**p))
-    for i in range(len(wl.R)):
-        d.add_sphere(wl.x[i], wl.R[i], wl.rho[i], u=wl.u[i], w=wl.w[i])
+    if len(wl.R):
+        d.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
     if wl.ramp is not None:
         r = wl.ramp
         d.set_mode(0, O.MODE_PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])

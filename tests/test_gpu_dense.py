@@ -8,7 +8,8 @@ block per sphere with its cells staged in LDS) against the oracle.
   FP64, both kernels, every sphere and the final fields against the oracle,
   and the kernels bit for bit against each other;
 * the dense suspension at 96^3 with 156 spheres D = 12 (16 % solids, gaps
-  >= 1, at rest, weak gravity), 30 steps, FP64;
+  >= 1, at rest, weak gravity), 100 steps, FP64, every boundary pass
+  (several blocks per sphere, one block per sphere, fused into the sweep);
 * the dense suspension at its full size (384^3, 10,000 spheres, FP32
   storage, the automatic kernel choice), where the oracle cannot run: the
   closure of the momentum exchange in fluid at rest (Sec. 2.2, missing
@@ -73,10 +74,10 @@ def _compare_fields(g, o, tol=TOL):
 def test_dense_agitated_fp64_both_kernels():
     wl = W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)
     P = len(wl.R)
-    _case(f"agitated 48^3, {P} spheres, FP64, (DEM, map) kernels (1,1) (2,1) (2,2)")
+    _case(f"agitated 48^3, {P} spheres, FP64, (DEM, map) kernels (1,1) (2,1) (2,2) (2,3)")
     o = oracle_domain(wl)
     gs = [gpu_domain(wl, dem_kernel=1, map_kernel=1), gpu_domain(wl, dem_kernel=2, map_kernel=1),
-          gpu_domain(wl, dem_kernel=2, map_kernel=2)]
+          gpu_domain(wl, dem_kernel=2, map_kernel=2), gpu_domain(wl, dem_kernel=2, map_kernel=3)]
     u_scale = float(np.abs(wl.u).max())
     F_scale = 0.0
     contacts = lub = 0
@@ -103,12 +104,14 @@ def test_dense_agitated_fp64_both_kernels():
 def test_dense_96_fp64():
     wl = W.dense(0, n=96, count=156)
     P = len(wl.R)
-    _case(f"dense 96^3, {P} spheres D=12, FP64, 30 steps, (DEM, map) kernels auto, (2, auto), (1, 1)")
+    _case(f"dense 96^3, {P} spheres D=12, FP64, 100 steps, (DEM, map) kernels auto, (2, auto), (1, 1), "
+          f"(auto, fused)")
     o = oracle_domain(wl)
-    gs = [gpu_domain(wl), gpu_domain(wl, dem_kernel=2), gpu_domain(wl, dem_kernel=1, map_kernel=1)]
+    gs = [gpu_domain(wl), gpu_domain(wl, dem_kernel=2), gpu_domain(wl, dem_kernel=1, map_kernel=1),
+          gpu_domain(wl, map_kernel=3)]
     wgt = 4.0 / 3.0 * np.pi * 6.0 ** 3 * (wl.rho[0] - 1.0) * 2e-6
     done = 0
-    for chk in (1, 10, 30):
+    for chk in (1, 10, 30, 100):
         o.step(chk - done)
         for g in gs:
             g.step(chk - done)

@@ -97,14 +97,14 @@ def test_wide_rows(storage):
     assert err <= 12 * 2.0 ** -11 * dev, (err, dev)
 
 
-@pytest.mark.parametrize("coll", [O.TRT_AB, O.TRT_B, O.SRT])
-def test_body_force_fluid_and_fixed_sphere(coll):
+@pytest.mark.parametrize("coll,mk", [(O.TRT_AB, 0), (O.TRT_B, 0), (O.SRT, 0), (O.TRT_AB, 3)])
+def test_body_force_fluid_and_fixed_sphere(coll, mk):
     """Guo forcing (the oracle's moment-space form against the sweep's
     velocity-space form): a periodic random field under a body force, then a
     fixed sphere in it (momentum exchange and the shell under forcing)."""
     n = (17, 12, 16)
     a = (2e-5, -1e-5, 3e-5)
-    _case(f"body force {a} on {n}, collision {coll}")
+    _case(f"body force {a} on {n}, collision {coll}, map_kernel {mk}")
     wl = W.Workload("forced", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 0), nu=0.03,
                                             collision=coll, max_spheres=1, body_force=a),
                     np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
@@ -118,7 +118,7 @@ def test_body_force_fluid_and_fixed_sphere(coll):
     _compare_fields(g, o)
     wl.x, wl.R, wl.rho = np.array([[8.3, 6.1, 7.7]]), np.array([3.2]), np.array([1.0])
     wl.u, wl.w = np.zeros((1, 3)), np.zeros((1, 3))
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     o.set_mode(0, O.MODE_FIXED)
     from paper_2003_01490_amd import lbmdem as L
     g.set_mode(0, L.FIXED)
@@ -180,16 +180,17 @@ def test_couette_channel_and_moving_walls():
     _compare_fields(g, o)
 
 
-def test_walls_on_all_axes():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_walls_on_all_axes(mk):
     n = (12, 11, 10)
-    _case(f"closed box {n}")
+    _case(f"closed box {n} map_kernel {mk}")
     wl = W.Workload("box", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(1, 1, 1), nu=0.05,
                                          max_spheres=2),
                     np.array([[4.3, 5.1, 4.9], [8.0, 5.5, 5.2]]), np.array([1.9, 1.7]),
                     np.array([2.0, 3.0]), np.array([[0.01, 0.0, -0.005], [-0.01, 0.002, 0.0]]),
                     np.zeros((2, 3)), 40)
     f = random_pdf(n, seed=12)
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     o.set_pdf(f)
     g.set_pdf(f)
     o.step(wl.steps)
@@ -202,9 +203,10 @@ def test_walls_on_all_axes():
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
-def test_mapping_bit_exact(storage):
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_mapping_bit_exact(storage, mk):
     n = (30, 28, 26)
-    _case(f"mapping {n} storage {storage}")
+    _case(f"mapping {n} storage {storage} map_kernel {mk}")
     rng = np.random.default_rng(5)
     xs, Rs = [], []
     # centres on cell centres with Pythagorean radii: cell centres lie exactly
@@ -230,7 +232,7 @@ def test_mapping_bit_exact(storage):
     wl = W.Workload("map", W.base_params(nx=n[0], ny=n[1], nz=n[2], max_spheres=len(xs)),
                     np.array(xs), np.array(Rs), np.full(len(xs), 2.0), np.zeros((len(xs), 3)),
                     np.zeros((len(xs), 3)), 0)
-    o, g = oracle_domain(wl), gpu_domain(wl, storage=storage)
+    o, g = oracle_domain(wl), gpu_domain(wl, storage=storage, map_kernel=mk)
     cg, og = g.flags()
     co, oo = o.flags()
     assert np.array_equal(cg, co)
@@ -239,15 +241,16 @@ def test_mapping_bit_exact(storage):
     assert co[10, 10, 15] == O.SOLID and og[10, 10, 15] == 0  # the shared tie cell
 
 
-def test_fixed_sphere_forces_on_random_field():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_fixed_sphere_forces_on_random_field(mk):
     n = (20, 18, 22)
-    _case(f"fixed sphere forces {n}")
+    _case(f"fixed sphere forces {n} map_kernel {mk}")
     wl = W.Workload("fixed", W.base_params(nx=n[0], ny=n[1], nz=n[2], nu=0.02, max_spheres=2),
                     np.array([[9.3, 8.7, 11.2], [2.0, 3.0, 1.0 + 3.1 + 0.3]]), np.array([4.1, 3.1]),
                     np.array([2.0, 2.0]), np.array([[0.01, -0.02, 0.005], [0.0, 0.0, 0.0]]),
                     np.array([[0.001, 0.002, -0.003], [0.0, 0.001, 0.0]]), 0)
     f = random_pdf(n, seed=3, u0=(0.01, 0.0, -0.01))
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     for dom in (o, g):
         for i in range(2):
             dom.set_mode(i, O.MODE_FIXED)
@@ -264,11 +267,11 @@ def test_fixed_sphere_forces_on_random_field():
     _compare_fields(g, o)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_settling_sphere_32_fp64(seed):
+@pytest.mark.parametrize("seed,mk", [(0, 0), (1, 0), (0, 3)])
+def test_settling_sphere_32_fp64(seed, mk):
     wl = W.settling_32(seed)
-    _case(f"settling_32 seed {seed} FP64, {wl.steps} steps")
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    _case(f"settling_32 seed {seed} FP64, {wl.steps} steps, map_kernel {mk}")
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     sc = Scales(weight(wl))
     done = 0
     for chk in (1, 10, 60, 150, 300):
@@ -282,13 +285,14 @@ def test_settling_sphere_32_fp64(seed):
     _compare_fields(g, o)
 
 
-def test_contact_variant_fp64():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_contact_variant_fp64(mk):
     """Contact and lubrication with the wall; the workgroup DEM kernel (LDS
     variant) and the one-thread-per-sphere one side by side."""
     wl = W.contact_32(0)
-    _case(f"contact_32 FP64, {wl.steps} steps, DEM kernels 1 and 2")
+    _case(f"contact_32 FP64, {wl.steps} steps, DEM kernels 1 and 2, map_kernel {mk}")
     o = oracle_domain(wl)
-    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
+    gs = [gpu_domain(wl, dem_kernel=1, map_kernel=mk), gpu_domain(wl, dem_kernel=2, map_kernel=mk)]
     sc = Scales(weight(wl))
     saw_contact = saw_lub = False
     done = 0
@@ -313,16 +317,17 @@ def test_contact_variant_fp64():
         _compare_fields(g, o)
 
 
-def test_two_spheres_oblique_collision_fp64():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_two_spheres_oblique_collision_fp64(mk):
     n = (40, 24, 24)
-    _case("two spheres colliding, periodic, DEM kernels 1 and 2")
+    _case(f"two spheres colliding, periodic, DEM kernels 1 and 2, map_kernel {mk}")
     wl = W.Workload("pair", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 1), nu=0.02,
                                           tc=30.0, max_spheres=2),
                     np.array([[12.0, 12.1, 11.8], [12.0 + 8.45, 12.9, 12.2]]), np.array([4.0, 4.2]),
                     np.array([2.0, 3.0]), np.array([[0.04, 0.0, 0.0], [-0.04, 0.0, 0.0]]),
                     np.zeros((2, 3)), 120)
     o = oracle_domain(wl)
-    gs = [gpu_domain(wl, dem_kernel=1), gpu_domain(wl, dem_kernel=2)]
+    gs = [gpu_domain(wl, dem_kernel=1, map_kernel=mk), gpu_domain(wl, dem_kernel=2, map_kernel=mk)]
     done = 0
     saw = False
     sc = [Scales(), Scales()]
@@ -345,15 +350,16 @@ def test_two_spheres_oblique_collision_fp64():
         _compare_fields(g, o)
 
 
-def test_prescribed_ramp_and_release():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_prescribed_ramp_and_release(mk):
     n = (24, 24, 40)
-    _case("prescribed ramp and release")
+    _case(f"prescribed ramp and release, map_kernel {mk}")
     wl = W.Workload("ramp", W.base_params(nx=n[0], ny=n[1], nz=n[2], nu=0.02,
                                           gravity=(0, 0, -2e-5), max_spheres=1),
                     np.array([[12.2, 11.9, 24.0]]), np.array([4.0]), np.array([3.0]),
                     np.zeros((1, 3)), np.zeros((1, 3)), 200,
                     ramp=dict(u_target=(0.0, 0.0, -0.04), c_acc=10.0, t_st=60.0, release_gap=12.0))
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     done = 0
     released = False
     sc = Scales(weight(wl))
@@ -371,15 +377,16 @@ def test_prescribed_ramp_and_release():
     _compare_fields(g, o)
 
 
-def test_update_spheres_reconstructs():
+@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+def test_update_spheres_reconstructs(mk):
     n = (18, 18, 18)
-    _case("teleport + reconstruction")
+    _case(f"teleport + reconstruction, map_kernel {mk}")
     wl = W.Workload("tele", W.base_params(nx=n[0], ny=n[1], nz=n[2], walls=(0, 0, 0), nu=0.04,
                                           max_spheres=1),
                     np.array([[8.3, 8.9, 9.1]]), np.array([3.6]), np.array([2.0]),
                     np.array([[0.01, 0.02, 0.0]]), np.array([[0.0, 0.0, 0.01]]), 0)
     f = random_pdf(n, seed=9, u0=(0.02, 0.0, 0.0))
-    o, g = oracle_domain(wl), gpu_domain(wl)
+    o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
     for dom in (o, g):
         dom.set_mode(0, O.MODE_FIXED)
         dom.set_pdf(f)
@@ -457,20 +464,20 @@ def _bitwise_equal(a, b):
     return all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("dem_kernel", [1, 2])
-def test_checkpoint_restore_bitwise(dem_kernel):
+@pytest.mark.parametrize("dem_kernel,mk", [(1, 0), (2, 0), (2, 3)])
+def test_checkpoint_restore_bitwise(dem_kernel, mk):
     """Continuing from a checkpoint equals continuing the saved domain bit for
     bit (contact history, averaging memory, boundary values included)."""
     from paper_2003_01490_amd import lbmdem as L
 
     wl = W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)
-    _case(f"checkpoint, agitated 48^3, DEM kernel {dem_kernel}")
-    g = gpu_domain(wl, dem_kernel=dem_kernel)
+    _case(f"checkpoint, agitated 48^3, DEM kernel {dem_kernel}, map_kernel {mk}")
+    g = gpu_domain(wl, dem_kernel=dem_kernel, map_kernel=mk)
     g.step(30)
     blob = g.save()
     g.step(40)
     ref = _state_bits(g)
-    h = gpu_domain(wl, dem_kernel=dem_kernel)
+    h = gpu_domain(wl, dem_kernel=dem_kernel, map_kernel=mk)
     h.step(3)  # a different state, overwritten by the restore
     h.restore(blob)
     h.step(40)
