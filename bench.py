@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--max-steps", type=int, default=6000, help="serving stream: step cap per request")
     ap.add_argument("--chunk", type=int, default=100, help="serving stream: steps per batch call")
     ap.add_argument("--serve-baseline", action="store_true", help="serving stream: also run FIFO one at a time")
+    ap.add_argument("--map-kernel", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="particle-link boundary pass (default: the configuration's automatic choice)")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="run the DEM beside the sweep on a second stream (1, default) or after it (0)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -282,6 +284,8 @@ def main():
     wl = make_workload(args.workload, args.seed)
     cfg = _gpu_params(wl, storage)
     cfg.overlap = args.overlap
+    if args.map_kernel is not None:
+        cfg.map_kernel = args.map_kernel
     dev = torch.device("cuda:0")
     dom = L.Domain(cfg, device=dev)
     dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)

@@ -155,7 +155,7 @@ void bin_dims(const lbmdem_config& c, int* nb) {
 }
 
 struct Layout {
-  size_t pdf0, pdf1, flags, owner, claim, shellstamp, stage, slot, slot_stamp, mbins;
+  size_t pdf0, pdf1, flags, owner, claim, shellstamp, cellw, stage, slot, slot_stamp, mbins;
   size_t x, u, w, xmap, R, rho, m, I, mode, presc, tpresc, Fprev, prev_valid, Ffp, Fraw, Fold,
       old_valid, diag, Fnew, hist_id, hist_d, nbr, nbr_n, x2, u2, w2, order, bins, ctl, partial, status;
   size_t total;
@@ -178,6 +178,7 @@ Layout make_layout(const lbmdem_config& c) {
   L.owner = take(4 * N);
   L.claim = take(8 * N);
   L.shellstamp = take(4 * N);
+  L.cellw = take(use_fused(c) ? 4 * N : 0);  // fused step: flags | (owner + 1) << 8
   L.stage = take(8 * N);
   // fused step only (transient, so not part of a checkpoint)
   {
@@ -540,6 +541,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.owner = (int32_t*)(base + L.owner);
   d.claim = (unsigned long long*)(base + L.claim);
   d.shellstamp = (uint32_t*)(base + L.shellstamp);
+  d.cellw = use_fused(*cfg) ? (uint32_t*)(base + L.cellw) : nullptr;
   DevParticles& p = d.p;
   p.x = (double*)(base + L.x);
   p.u = (double*)(base + L.u);

@@ -21,6 +21,7 @@ __global__ void k_init(DevDomain d) {
     d.owner[c] = -1;
     d.claim[c] = 0ull;
     d.shellstamp[c] = 0u;
+    if (d.cellw) d.cellw[c] = wall ? F_WALL : 0u;
     for (int q = 0; q < Q; ++q) {
       a[(size_t)q * N + c] = T(0.0f);
       b[(size_t)q * N + c] = T(0.0f);

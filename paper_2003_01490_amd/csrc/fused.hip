@@ -6,8 +6,8 @@
 // reads anyway, instead of by a separate pass over the spheres' surfaces.
 //
 // One block per tile of fbx x fby cells in one z plane:
-//   1. the cell flags and, for solid cells, the owners of the tile and a
-//      one-cell halo are staged in LDS;
+//   1. the cell words (flag byte and owner) of the tile and a one-cell halo
+//      are staged in LDS, row by row;
 //   2. every fluid cell lists its links (directions q whose cell x + c_q is
 //      solid) and every solid cell its missing links (y - c_q a wall or another
 //      sphere's solid); the spheres they belong to form the tile's table;
@@ -17,9 +17,10 @@
 //      (MEM_CLI) from f~_q(x), f~_qbar(x) and f~_q(x - c_q), its force and the
 //      torque about the sphere centre, all in FP64 with the arithmetic of the
 //      sphere-centric boundary pass;
-//   4. the forces and torques of the tile are summed per sphere in link order
-//      (fixed order, no atomics) and stored, stamped with the step, in the
-//      sphere's slot for this tile; k_force_reduce sums a sphere's slots;
+//   4. the forces and torques of the tile are summed per sphere exactly (an
+//      order-independent fixed-point sum, see fx_add) and stored, stamped with
+//      the step, in the sphere's slot for this tile; k_force_reduce sums a
+//      sphere's slots in slot order;
 //   5. each cell replaces the values it pulled from solid cells by its
 //      boundary values (rounded to the storage type, as if stored and
 //      reloaded) and collides as in the plain sweep.
@@ -40,6 +41,25 @@ constexpr int KCX[Q] = {0, 0, 0, -1, 1, 0, 0, -1, 1, -1, 1, 0, 0, -1, 1, 0, 0, -
 constexpr int KCY[Q] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, -1, 0, 0, 1, -1, 0, 0};
 constexpr int KCZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1};
 constexpr int KOPP[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 16, 15, 18, 17, 12, 11, 14, 13};
+
+// the velocity set packed into constants (no memory access for a per-lane q):
+// c_q + 1 in two bits per axis, the opposite direction in five bits
+constexpr unsigned long long pack_c(const int* c) {
+  unsigned long long v = 0;
+  for (int q = 0; q < Q; ++q) v |= (unsigned long long)(c[q] + 1) << (2 * q);
+  return v;
+}
+constexpr unsigned long long PCX = pack_c(KCX), PCY = pack_c(KCY), PCZ = pack_c(KCZ);
+constexpr unsigned long long pack_opp(int lo) {
+  unsigned long long v = 0;
+  for (int q = lo; q < lo + 12 && q < Q; ++q) v |= (unsigned long long)KOPP[q] << (5 * (q - lo));
+  return v;
+}
+constexpr unsigned long long POPP0 = pack_opp(0), POPP1 = pack_opp(12);
+__device__ __forceinline__ int cq_of(unsigned long long pk, int q) { return (int)((pk >> (2 * q)) & 3ull) - 1; }
+__device__ __forceinline__ int opp_of(int q) {
+  return q < 12 ? (int)((POPP0 >> (5 * q)) & 31ull) : (int)((POPP1 >> (5 * (q - 12))) & 31ull);
+}
 
 // the value the plain sweep would pull after the boundary pass stored v
 template <typename T>
@@ -101,32 +121,52 @@ __device__ __forceinline__ int slot_index(const DevDomain& d, const double* xs, 
   return (rel[2] * d.sl_ny + rel[1]) * d.sl_nx + rel[0];
 }
 
+// Tile partials are accumulated exactly, in any order: each value v is split
+// into h = rint(v 2^30) and l = rint((v - h 2^-30) 2^80) (the subtraction is
+// exact), and the two integer parts are summed with 64-bit LDS atomics.  The
+// partial is the exact sum of the values rounded to 2^-81, rounded once to
+// FP64: deterministic, and at least as accurate as a sequential FP64 sum.
+__device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long long* lo, double v) {
+  const double h = rint(v * 0x1p30);
+  const double l = rint((v - h * 0x1p-30) * 0x1p80);
+  atomicAdd(hi, (unsigned long long)(long long)h);
+  atomicAdd(lo, (unsigned long long)(long long)l);
+}
+__device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo) {
+  return (double)(long long)hi * 0x1p-30 + (double)(long long)lo * 0x1p-80;
+}
+
+// cell word of the fused step: flag byte | (owner + 1) << 8
+constexpr uint32_t CW_WALL = F_WALL;
+__device__ __forceinline__ int cw_owner(uint32_t w) { return (int)(w >> 8) - 1; }
+
 // (at most 128 VGPRs: four waves per SIMD)
 template <typename T, bool FORCED>
 __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep_fused(DevDomain d) {
   using C = typename Store<T>::C;
-  __shared__ uint8_t sfl[FT_HALO_MAX];
-  __shared__ int sown[FT_HALO_MAX];
+  __shared__ uint32_t swd[FT_HALO_MAX];
   __shared__ int hkey[FT_HASH], hslot[FT_HASH];
   __shared__ int tab_id[FT_TABLE];
   __shared__ double tab[FT_TABLE][10];  // x (3), R, u (3), w (3)
+  __shared__ unsigned long long fxh[FT_TABLE][6], fxl[FT_TABLE][6];
   __shared__ uint32_t lk[FT_ROUND];
+  __shared__ double lval[FT_ROUND];
   __shared__ double lres[6][FT_ROUND];
   __shared__ int lslot[FT_ROUND];
-  __shared__ double lval[FT_ROUND];
   __shared__ int wsum[FT_THREADS / 64];
   __shared__ int s_ntab, s_err;
 
   if (!step_live(d.ctl)) return;  // uniform over the grid
   const int BX = (int)blockDim.x, BY = (int)blockDim.y, nthr = BX * BY;
-  const int tid = (int)threadIdx.x + BX * (int)threadIdx.y;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y;
+  const int tid = tx + BX * ty;
   const int lane = tid & 63, wid = tid >> 6, nw = (nthr + 63) >> 6;
   const int tl = (int)blockIdx.x;
   const int bx = tl % d.fgx, rr = tl / d.fgx, by = rr % d.fgy, z = rr / d.fgy;
   const int x0 = bx * BX, y0 = by * BY;
-  const int x = x0 + (int)threadIdx.x, y = y0 + (int)threadIdx.y;
+  const int x = x0 + tx, y = y0 + ty;
   const bool in = x < d.nx && y < d.ny;
-  const int HX = BX + 2, HY = BY + 2, NH = HX * HY * 3;
+  const int HX = BX + 2, HY = BY + 2;
   const int cur = d.ctl->cur;
   const uint32_t stamp = d.ctl->stamp;
   const T* src = (const T*)(cur ? d.pdf[1] : d.pdf[0]);
@@ -134,38 +174,58 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
   const size_t N = (size_t)d.N;
   const unsigned int idx = in ? (unsigned int)cidx(d, x, y, z) : 0u;
 
+  // the cell's own pulls (walls replaced), in flight while the links are formed
+  C g[Q];
+  if (in) pull_cell<T, false>(d, src, x, y, z, idx, g);
+
   for (int h = tid; h < FT_HASH; h += nthr) hkey[h] = -1;
+  for (int k = tid; k < FT_TABLE * 6; k += nthr) {
+    (&fxh[0][0])[k] = 0ull;
+    (&fxl[0][0])[k] = 0ull;
+  }
   if (tid == 0) {
     s_ntab = 0;
     s_err = 0;
   }
 
-  // 1. flags and owners of the tile and its halo (cells beyond a wall layer
-  // count as wall; periodic axes wrap)
-  for (int h0 = tid; h0 < NH; h0 += 4 * nthr) {
-    long long cc[4];
-    uint8_t fl[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int h = h0 + u * nthr;
-      cc[u] = -1;
-      fl[u] = F_WALL;
-      if (h < NH) {
-        const int gx = x0 - 1 + h % HX, gy = y0 - 1 + (h / HX) % HY, gz = z - 1 + h / (HX * HY);
-        const bool out = (d.walls[0] && (gx < 0 || gx >= d.nx)) || (d.walls[1] && (gy < 0 || gy >= d.ny)) ||
-                         (d.walls[2] && (gz < 0 || gz >= d.nz));
-        if (!out) cc[u] = cidx(d, wrapmod(gx, d.nx), wrapmod(gy, d.ny), wrapmod(gz, d.nz));
-      }
+  // 1. cell words of the tile and a one-cell halo, row by row (cells beyond a
+  // wall layer count as wall; periodic axes wrap)
+  {
+    const int xi = x0 + tx;  // interior column of this thread
+    const bool xin = xi < d.nx;
+    const int xe = tx == 0 ? x0 - 1 : x0 + BX;  // edge columns (threads 0 and 1)
+    int xew = xe;
+    bool xeo = false;
+    if (xe < 0 || xe >= d.nx) {
+      if (d.walls[0]) xeo = true;
+      else xew = wrapmod(xe, d.nx);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (cc[u] >= 0) fl[u] = d.flags[cc[u]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int h = h0 + u * nthr;
-      if (h < NH) {
-        sfl[h] = fl[u];
-        sown[h] = (cc[u] >= 0 && (fl[u] & F_SOLID)) ? d.owner[cc[u]] : -1;
+    int xiw = xi;
+    bool xio = false;
+    if (!xin) {
+      if (d.walls[0]) xio = true;
+      else xiw = wrapmod(xi, d.nx);
+    }
+    // row r = hy + HY hz of the halo: thread row ty takes r = ty, ty + BY, ...
+    int hy = ty, hz = 0;
+    while (hy >= HY) {
+      hy -= HY;
+      ++hz;
+    }
+    for (; hz < 3;) {
+      int gy = y0 - 1 + hy, gz = z - 1 + hz;
+      const bool rowout = (d.walls[1] && (gy < 0 || gy >= d.ny)) || (d.walls[2] && (gz < 0 || gz >= d.nz));
+      if (gy < 0) gy += d.ny;
+      else if (gy >= d.ny) gy = gy - d.ny < d.ny ? gy - d.ny : wrapmod(gy, d.ny);
+      gz = wrapi(gz, d.nz);
+      const size_t rb = ((size_t)gz * d.ny + gy) * d.nx;
+      const int hb = HX * (hy + HY * hz);
+      swd[hb + tx + 1] = (rowout || xio) ? CW_WALL : d.cellw[rb + xiw];
+      if (tx < 2) swd[hb + (tx == 0 ? 0 : BX + 1)] = (rowout || xeo) ? CW_WALL : d.cellw[rb + xew];
+      hy += BY;
+      while (hy >= HY) {
+        hy -= HY;
+        ++hz;
       }
     }
   }
@@ -173,28 +233,28 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
 
   // 2. the cell's links: fluid cell -> directions q with x + c_q solid;
   // solid cell -> missing links (y - c_q a wall or another sphere's solid)
-  const int hc = ((int)threadIdx.x + 1) + HX * (((int)threadIdx.y + 1) + HY);
-  const uint8_t fc = in ? sfl[hc] : (uint8_t)F_WALL;
+  const int hc = (tx + 1) + HX * ((ty + 1) + HY);
+  const uint32_t wc = in ? swd[hc] : CW_WALL;
   uint32_t mask = 0u;
-  const bool fluid = in && !(fc & (F_SOLID | F_WALL));
+  const bool fluid = in && !(wc & (F_SOLID | F_WALL));
   if (fluid) {
-#pragma unroll
-    for (int q = 1; q < Q; ++q)
-      if (sfl[hc + KCX[q] + HX * (KCY[q] + HY * KCZ[q])] & F_SOLID) mask |= 1u << q;
     int last = -1;
 #pragma unroll
-    for (int q = 1; q < Q; ++q)
-      if (mask & (1u << q)) {
-        const int o = sown[hc + KCX[q] + HX * (KCY[q] + HY * KCZ[q])];
+    for (int q = 1; q < Q; ++q) {
+      const uint32_t wy = swd[hc + KCX[q] + HX * (KCY[q] + HY * KCZ[q])];
+      if (wy & F_SOLID) {
+        mask |= 1u << q;
+        const int o = cw_owner(wy);
         if (o != last && o >= 0 && o < d.P) tile_insert(hkey, o, &s_err);
         last = o;
       }
-  } else if (in && (fc & F_SOLID)) {
-    const int own = sown[hc];
+    }
+  } else if (in && (wc & F_SOLID)) {
+    const int own = cw_owner(wc);
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const int hz = hc - (KCX[q] + HX * (KCY[q] + HY * KCZ[q]));
-      if ((sfl[hz] & F_WALL) || ((sfl[hz] & F_SOLID) && sown[hz] != own)) mask |= 1u << q;
+      const uint32_t wz = swd[hc - (KCX[q] + HX * (KCY[q] + HY * KCZ[q]))];
+      if ((wz & F_WALL) || ((wz & F_SOLID) && cw_owner(wz) != own)) mask |= 1u << q;
     }
     if (mask && own >= 0 && own < d.P) tile_insert(hkey, own, &s_err);
   }
@@ -243,12 +303,7 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
     tab[s][c] = c < 3 ? d.p.x[3 * i + c] : (c == 3 ? d.p.R[i] : (c < 7 ? d.p.u[3 * i + c - 4] : d.p.w[3 * i + c - 7]));
   }
 
-  // the cell's own pulls (walls replaced), in flight during the link rounds
-  C g[Q];
-  if (in) pull_cell<T, false>(d, src, x, y, z, idx, g);
-
   // 3./4. link rounds
-  double acc0 = 0.0, acc1 = 0.0;  // (slot, component) j = tid and j = tid + nthr
   const bool solid_cell = !fluid;
   for (int r0 = 0; r0 < total; r0 += FT_ROUND) {
     __syncthreads();  // previous round's buffers are free; the table is loaded
@@ -258,7 +313,7 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
       for (int q = 1; q < Q; ++q)
         if (mask & (1u << q)) {
           if (e >= r0 && e < r0 + FT_ROUND)
-            lk[e - r0] = (uint32_t)tid | ((uint32_t)q << 9) | (solid_cell ? (1u << 14) : 0u);
+            lk[e - r0] = (uint32_t)tx | ((uint32_t)ty << 9) | ((uint32_t)q << 18) | (solid_cell ? (1u << 23) : 0u);
           ++e;
         }
     }
@@ -266,24 +321,24 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
     const int nr = min(FT_ROUND, total - r0);
     if (tid < nr) {
       const uint32_t e = lk[tid];
-      const int ct = (int)(e & 511u), q = (int)((e >> 9) & 31u);
-      const bool missing = (e >> 14) & 1u;
-      const int ctx = ct % BX, cty = ct / BX;
+      const int ctx = (int)(e & 511u), cty = (int)((e >> 9) & 511u), q = (int)((e >> 18) & 31u);
+      const bool missing = (e >> 23) & 1u;
       const int cxx = x0 + ctx, cyy = y0 + cty;
       const int hcc = (ctx + 1) + HX * ((cty + 1) + HY);
-      const int c[3] = {CX[q], CY[q], CZ[q]};
+      const int c[3] = {cq_of(PCX, q), cq_of(PCY, q), cq_of(PCZ, q)};
       const int offq = c[0] + HX * (c[1] + HY * c[2]);
       const double wq = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] == 1 ? 1.0 / 18 : 1.0 / 36;
-      const int s = tile_slot(hkey, hslot, missing ? sown[hcc] : sown[hcc + offq]);
-      double Fq[3] = {0.0, 0.0, 0.0}, arm[3] = {0.0, 0.0, 0.0};
+      const int s = tile_slot(hkey, hslot, cw_owner(missing ? swd[hcc] : swd[hcc + offq]));
+      lslot[tid] = s;
       if (s >= 0) {
         const double xp[3] = {tab[s][0], tab[s][1], tab[s][2]};
+        double Fq[3], arm[3];
         if (!missing) {
           const double R = tab[s][3];
           const double up[3] = {tab[s][4], tab[s][5], tab[s][6]}, wp[3] = {tab[s][7], tab[s][8], tab[s][9]};
           const size_t cc = (size_t)cidx(d, cxx, cyy, z);
-          const int qb = OPP[q];
-          const bool cli = d.boundary == 0 && !(sfl[hcc - offq] & (F_SOLID | F_WALL));
+          const int qb = opp_of(q);
+          const bool cli = d.boundary == 0 && !(swd[hcc - offq] & (F_SOLID | F_WALL));
           const T gq = src[(size_t)q * N + cc];
           const T gqb = src[(size_t)qb * N + cc];
           T gm = (T)0.0f;
@@ -317,26 +372,35 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
           arm[1] = min_image(((double)cyy + 0.5) - xp[1], d.ny, d.walls[1]) - 0.5 * c[1];
           arm[2] = min_image(((double)z + 0.5) - xp[2], d.nz, d.walls[2]) - 0.5 * c[2];
         }
+        lres[0][tid] = Fq[0];
+        lres[1][tid] = Fq[1];
+        lres[2][tid] = Fq[2];
+        lres[3][tid] = arm[1] * Fq[2] - arm[2] * Fq[1];
+        lres[4][tid] = arm[2] * Fq[0] - arm[0] * Fq[2];
+        lres[5][tid] = arm[0] * Fq[1] - arm[1] * Fq[0];
       }
-      lres[0][tid] = Fq[0];
-      lres[1][tid] = Fq[1];
-      lres[2][tid] = Fq[2];
-      lres[3][tid] = arm[1] * Fq[2] - arm[2] * Fq[1];
-      lres[4][tid] = arm[2] * Fq[0] - arm[0] * Fq[2];
-      lres[5][tid] = arm[0] * Fq[1] - arm[1] * Fq[0];
-      lslot[tid] = s;
     }
     __syncthreads();
-    // per-sphere sums of the round, in link order
-    if (tid < 6 * ntab) {
-      const int s = tid / 6, comp = tid % 6;
-      for (int k = 0; k < nr; ++k)
-        if (lslot[k] == s) acc0 += lres[comp][k];
-    }
-    if (tid + nthr < 6 * ntab) {
-      const int s = (tid + nthr) / 6, comp = (tid + nthr) % 6;
-      for (int k = 0; k < nr; ++k)
-        if (lslot[k] == s) acc1 += lres[comp][k];
+    // each cell sums its own links of the round (usually all of one sphere)
+    // and adds the sums to the tile accumulators (exact, so any grouping
+    // gives the same bits)
+    if (cnt && off < r0 + nr && off + cnt > r0) {
+      const int e0 = max(off, r0) - r0, e1 = min(off + cnt, r0 + nr) - r0;
+      int sa = -1;
+      double a[6] = {0, 0, 0, 0, 0, 0};
+      for (int e = e0; e < e1; ++e) {
+        const int se = lslot[e];
+        if (se < 0) continue;
+        if (se != sa) {
+          if (sa >= 0)
+            for (int k = 0; k < 6; ++k) fx_add(&fxh[sa][k], &fxl[sa][k], a[k]);
+          sa = se;
+          for (int k = 0; k < 6; ++k) a[k] = 0.0;
+        }
+        for (int k = 0; k < 6; ++k) a[k] += lres[k][e];
+      }
+      if (sa >= 0)
+        for (int k = 0; k < 6; ++k) fx_add(&fxh[sa][k], &fxl[sa][k], a[k]);
     }
     // the cell's boundary values of this round replace its pulls from solids
     if (fluid && off < r0 + FT_ROUND && off + cnt > r0) {
@@ -351,8 +415,9 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
   }
 
   // the tile's partial of each sphere into that sphere's slot for this tile
-  for (int j = tid, u = 0; u < 2; ++u, j += nthr) {
-    if (j >= 6 * ntab || total == 0) continue;
+  // (after every cell's sums have reached the accumulators)
+  __syncthreads();
+  for (int j = tid; j < 6 * ntab && total > 0; j += nthr) {
     const int s = j / 6, comp = j % 6, i = tab_id[s];
     const double xs[3] = {tab[s][0], tab[s][1], tab[s][2]};
     const int sl = slot_index(d, xs, tab[s][3], bx, by, z);
@@ -360,14 +425,14 @@ __global__ __launch_bounds__(FT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8
       atomicOr(d.status, ST_TILE_FULL);
       continue;
     }
-    d.slot[((size_t)i * d.sl_per + sl) * 6 + comp] = u ? acc1 : acc0;
+    d.slot[((size_t)i * d.sl_per + sl) * 6 + comp] = fx_value(fxh[s][comp], fxl[s][comp]);
     if (comp == 0) d.slot_stamp[(size_t)i * d.sl_per + sl] = stamp;
   }
 
   // 5. collide and store (every cell, so that wavefronts write whole lines)
   if (in)
-    collide_store<T, FORCED>(d, dst, idx, fc, g, (C)d.s_plus, (C)d.s_minus, (C)(d.s_bulk_shell - d.s_plus),
-                             (C)(d.s_bulk_other - d.s_plus));
+    collide_store<T, FORCED>(d, dst, idx, (uint8_t)(wc & 0xFFu), g, (C)d.s_plus, (C)d.s_minus,
+                             (C)(d.s_bulk_shell - d.s_plus), (C)(d.s_bulk_other - d.s_plus));
 }
 
 // Resolved force and torque of each sphere: its tile partials of this step,

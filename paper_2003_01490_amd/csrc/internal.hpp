@@ -134,6 +134,7 @@ struct DevDomain {
   int32_t* owner;
   unsigned long long* claim;
   uint32_t* shellstamp;
+  uint32_t* cellw;   // fused step: flag byte | (owner + 1) << 8 per cell (NULL otherwise)
   DevParticles p;
   int P;           // spheres present
   int ZB;          // mapping blocks per sphere along z (slabs)

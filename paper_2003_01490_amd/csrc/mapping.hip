@@ -1252,6 +1252,25 @@ __device__ __forceinline__ bool wall_cell(const DevDomain& d, int i, int j, int 
          (d.walls[2] && (k == 0 || k == d.nz - 1));
 }
 
+// Rows of a box for the geometric mapping kernels: groups of 32 threads take
+// the (y, z) rows in turn and cover a row in steps of 32 cells.  Per row the
+// squared y and z offsets from a centre are formed once; per cell then
+// (dx dx + dy dy) + dz dz, the same rounding as cell_d2.
+struct RowPos {
+  double dy2, dz2;
+};
+__device__ __forceinline__ RowPos row_pos(const DevDomain& d, int jj, int kk, const double* xp) {
+#pragma clang fp contract(off)
+  const double dy = min_image(((double)jj + 0.5) - xp[1], d.ny, d.walls[1]);
+  const double dz = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]);
+  return RowPos{dy * dy, dz * dz};
+}
+__device__ __forceinline__ double row_d2(const DevDomain& d, int ii, const RowPos& r, const double* xp) {
+#pragma clang fp contract(off)
+  const double dx = min_image(((double)ii + 0.5) - xp[0], d.nx, d.walls[0]);
+  return (dx * dx + r.dy2) + r.dz2;
+}
+
 // Reconstruction inside a step (one block per sphere i): cells of i's solid
 // at the mapped positions (flags and owners in place) that are not solid at
 // the new positions, from neighbours fluid before (flags) and after
@@ -1280,19 +1299,30 @@ __global__ __launch_bounds__(256) void k_recon_geo(DevDomain d) {
     int o;
     return !(d.flags[y] & (F_SOLID | F_WALL)) && geo_state(d, yi, yj, yk, &o) != S_SOLID;
   };
-  FOR_BOX_CELLS(d, bx, 0, 1, {
-    if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
-      const long long c = cidx(d, ii, jj, kk);
-      int o;
-      if ((d.flags[c] & F_SOLID) && d.owner[c] == i && geo_state(d, ii, jj, kk, &o) != S_SOLID) {
-        const int k = atomicAdd(&ncand, 1);
-        if (k < RECON_LIST)
-          cand[k] = c;
-        else
-          reconstruct_with<T>(d, buf, ii, jj, kk, i, usable);  // list full: rebuild here
+  {
+    const int col = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+    for (int r = grp; r < bx.ext[1] * bx.ext[2]; r += ngrp) {
+      const int ty = r % bx.ext[1], tz = r / bx.ext[1];
+      const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
+      const int kk = d.walls[2] ? bx.lo[2] + tz : wrap_near(bx.lo[2] + tz, d.nz);
+      const RowPos po = row_pos(d, jj, kk, xo), pn = row_pos(d, jj, kk, xn);
+      if (po.dy2 + po.dz2 > R2) continue;  // the row misses the old ball
+      for (int tx = col; tx < bx.ext[0]; tx += 32) {
+        const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
+        if (row_d2(d, ii, po, xo) <= R2 && !(row_d2(d, ii, pn, xn) <= R2)) {
+          const long long c = cidx(d, ii, jj, kk);
+          int o;
+          if ((d.flags[c] & F_SOLID) && d.owner[c] == i && geo_state(d, ii, jj, kk, &o) != S_SOLID) {
+            const int k = atomicAdd(&ncand, 1);
+            if (k < RECON_LIST)
+              cand[k] = c;
+            else
+              reconstruct_with<T>(d, buf, ii, jj, kk, i, usable);  // list full: rebuild here
+          }
+        }
       }
     }
-  })
+  }
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -1318,18 +1348,29 @@ __global__ __launch_bounds__(256) void k_remap_geo(DevDomain d) {
     R2 = R * R;
     rs2 = rs * rs;
   }
-  FOR_BOX_CELLS(d, bx, 0, 1, {
-    if (!wall_cell(d, ii, jj, kk)) {
-      const double d2o = cell_d2(d, ii, jj, kk, xo), d2n = cell_d2(d, ii, jj, kk, xn);
+  const int col = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+  for (int r = grp; r < bx.ext[1] * bx.ext[2]; r += ngrp) {
+    const int ty = r % bx.ext[1], tz = r / bx.ext[1];
+    const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
+    const int kk = d.walls[2] ? bx.lo[2] + tz : wrap_near(bx.lo[2] + tz, d.nz);
+    if ((d.walls[1] && (jj == 0 || jj == d.ny - 1)) || (d.walls[2] && (kk == 0 || kk == d.nz - 1))) continue;
+    const RowPos po = row_pos(d, jj, kk, xo), pn = row_pos(d, jj, kk, xn);
+    if (po.dy2 + po.dz2 > rs2 && pn.dy2 + pn.dz2 > rs2) continue;  // the row misses both shell balls
+    for (int tx = col; tx < bx.ext[0]; tx += 32) {
+      const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
+      if (d.walls[0] && (ii == 0 || ii == d.nx - 1)) continue;
+      const double d2o = row_d2(d, ii, po, xo), d2n = row_d2(d, ii, pn, xn);
       if ((d2o <= R2) != (d2n <= R2) || (d2o <= rs2) != (d2n <= rs2)) {
         int own;
         const int st = geo_state(d, ii, jj, kk, &own);
         const long long c = cidx(d, ii, jj, kk);
-        d.flags[c] = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+        const uint8_t fl = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+        d.flags[c] = fl;
         if (st == S_SOLID) d.owner[c] = own;
+        d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (uint32_t)(own + 1) << 8 : 0u);
       }
     }
-  })
+  }
 }
 
 // End of a fused step: the mapping bins are emptied (by the positions they
@@ -1386,8 +1427,10 @@ __global__ void k_commit_full(DevDomain d) {
     const uint32_t v = d.stage32[c];
     const int st = (int)(v & 3u);
     if (st == S_WALL) continue;
-    d.flags[c] = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+    const uint8_t fl = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+    d.flags[c] = fl;
     if (st == S_SOLID) d.owner[c] = (int)(v >> 2) - 1;
+    d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (v >> 2) << 8 : 0u);
   }
 }
 
