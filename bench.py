@@ -1,17 +1,20 @@
 """Benchmark of the coupled LBM-DEM step on one MI355X.
 
-Default workload: single sphere-wall collision, 128x128x256 lattice, FP32
-population storage, D = 20, Stokes number 100 (the paper's St = 100 row),
-sphere released from the acceleration ramp one diameter above the wall.
-A step is one full pass of Alg. 1 on the GPU: fused stream-collide sweep,
-DEM sub-cycles, mapping update with reconstruction, boundary values and
-momentum-exchange partials for the next step.
+Default workload: the dense suspension of 24,000 spheres of diameter 12 in a
+512^3 lattice (periodic in x and y, walls in z, ~16 % solids, density ratio 2,
+gravity 2e-6, viscosity 0.02), FP32 population storage, and the same inputs
+with FP16 storage reported beside it.  A step is one full pass of Alg. 1 on
+the GPU: fused stream-collide sweep, DEM sub-cycles, mapping update with
+reconstruction, boundary values and momentum-exchange partials of the next
+step.
 
-Prints one JSON line: MLUPS over all cells, the roofline of the dominant kernel
-(the sweep, HBM bound; algorithmic bytes = 19 loads + 19 stores of the stored
-PDF type + 1 flag byte per cell; duration from HIP events around every sweep
-launch on the domain's stream), and the oracle timed on the host CPU on a
-bounded sample of the same workload.
+Prints one JSON line: MLUPS over all cells; the roofline of the dominant
+kernel (the sweep, HBM bound; algorithmic bytes = 19 loads + 19 stores of the
+stored PDF type + 1 flag byte per cell; duration from HIP events around every
+sweep launch on the domain's stream); the coupled step's algorithmic GB/s and
+fraction of the HBM peak; and the oracle timed on one pinned host core on a
+bounded sample of the same workload.  Other workloads: --workload
+sphere_wall | dense | dense512 | settling_32 | serve.
 """
 from __future__ import annotations
 
@@ -56,6 +59,16 @@ def make_workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
+def sweep_source_sha() -> str:
+    """SHA-256 over the sources the sweep kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("sweep.hip", "collide.hpp", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2003_01490_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_record(workload: str, storage: str):
     """HBM bytes per sweep launch measured with hardware counters (profiles/),
     valid only while the sweep source is the one that was measured."""
@@ -63,8 +76,7 @@ def traffic_record(workload: str, storage: str):
     import hashlib
     import re
 
-    src = os.path.join(ROOT, "paper_2003_01490_amd", "csrc", "sweep.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = sweep_source_sha()
     tag = {"f64": "FP64", "f32": "FP32", "f16": "FP16"}[storage]
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "pmc_traffic_*.md"))):
         for block in re.findall(r"```json\n(.*?)\n```", open(f).read(), re.S):
@@ -89,22 +101,40 @@ def cpu_sample(name, wl, seed):
 
 def cpu_baseline(wl, steps):
     """The oracle, single-threaded, on `steps` coupled steps of the given
-    lattice and spheres."""
+    lattice and spheres, with this process pinned to one host core while it
+    runs.  Returns MLUPS, seconds, the core."""
     import oracle as O
 
     keys = {f[0] for f in O.RefConfig._fields_}
     cfg = O.make_config(**{k: v for k, v in wl.params.items() if k in keys})
     d = O.RefDomain(cfg)
-    for i in range(len(wl.R)):
-        d.add_sphere(wl.x[i], wl.R[i], wl.rho[i], u=wl.u[i], w=wl.w[i])
+    if len(wl.R):
+        d.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
     if wl.ramp:
         r = wl.ramp
         d.set_mode(0, O.MODE_PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
-    t0 = time.perf_counter()
-    d.step(steps)
-    dt = time.perf_counter() - t0
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        d.step(steps)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     n = wl.params["nx"] * wl.params["ny"] * wl.params["nz"]
-    return n * steps / dt / 1e6, dt
+    return n * steps / dt / 1e6, dt, core
+
+
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
 
 
 def serve_bench(args):
@@ -245,15 +275,83 @@ def serve_bench(args):
     print(json.dumps(result))
 
 
+def run_domain(wl, storage_name, args, dev, profile_breakdown=True):
+    """One domain of the workload at one storage precision: warm-up, the timed
+    steps (HIP events around every sweep launch), a per-kernel-group breakdown
+    from extra steps, then the domain is closed."""
+    import torch
+
+    from paper_2003_01490_amd import lbmdem as L
+
+    storage = {"f64": L.STORE_F64, "f32": L.STORE_F32, "f16": L.STORE_F16}[storage_name]
+    cfg = _gpu_params(wl, storage)
+    cfg.overlap = args.overlap
+    if args.map_kernel is not None:
+        cfg.map_kernel = args.map_kernel
+    dom = L.Domain(cfg, device=dev)
+    try:
+        dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
+        if wl.ramp:
+            r = wl.ramp
+            dom.set_mode(0, L.PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
+        print(f"[bench] workload {wl.name} lattice {cfg.nx}x{cfg.ny}x{cfg.nz} spheres {len(wl.R)} "
+              f"storage {storage_name}", file=sys.stderr, flush=True)
+        dom.step(args.warmup)
+        dom.sync()
+        if args.copy_probe_mib:
+            nb = args.copy_probe_mib << 20
+            a = torch.empty(nb, dtype=torch.uint8, device=dev)
+            b = torch.empty(nb, dtype=torch.uint8, device=dev)
+            for _ in range(3):
+                L.device_copy(b, a, nb, dom.stream)
+            torch.cuda.synchronize()
+            del a, b
+        # timed region: HIP events around every sweep launch only (level 1)
+        dom.set_profiling(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dom.step(args.steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        dom.sync()
+        sweep_ms, sweep_n = dom.profile(0)
+        brk = {}
+        if profile_breakdown:
+            dom.set_profiling(2)
+            dom.step(min(args.steps, 50))
+            dom.sync()
+            brk = {k: dom.profile(j) for j, k in enumerate(("sweep", "dem_claims", "recon_commit_bc"))}
+        dom.set_profiling(0)
+        ncell = cfg.nx * cfg.ny * cfg.nz
+        nfluid = int((dom.field("flags") <= 1).sum())
+        sweep_avg_s = sweep_ms / max(sweep_n, 1) / 1e3
+        bytes_per_step = dom.sweep_bytes()
+        s0 = dom.sphere(0)
+        return {
+            "cfg": cfg, "ncell": ncell, "nfluid": nfluid, "elapsed": elapsed,
+            "ms_per_step": elapsed / args.steps * 1e3,
+            "mlups": ncell * args.steps / elapsed / 1e6,
+            "mflups_fluid": nfluid * args.steps / elapsed / 1e6,
+            "sweep_avg_s": sweep_avg_s, "bytes_per_step": bytes_per_step,
+            "breakdown": {k: round(ms / max(n, 1) * 1e3, 3) for k, (ms, n) in brk.items()},
+            "sphere0": {"z": float(s0["x"][2]), "uz": float(s0["u"][2]), "mode": s0["mode"]},
+        }
+    finally:
+        dom.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="sphere_wall")
-    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16"])
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="dense512")
+    ap.add_argument("--storage", default=None, choices=["f64", "f32", "f16"],
+                    help="population storage (default f32, with the f16 form of the dense "
+                         "workloads reported beside it)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="coupled steps of the oracle sample (default: about 15 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=64, help="serving stream: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serving stream: arrivals per second")
@@ -270,7 +368,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the path "
+                                   "would shard over several GPUs is described in the design notes)"}))
         raise SystemExit(2)
     if args.workload == "serve":
         serve_bench(args)
@@ -278,80 +377,40 @@ def main():
 
     import torch
 
-    from paper_2003_01490_amd import lbmdem as L
-
-    storage = {"f64": L.STORE_F64, "f32": L.STORE_F32, "f16": L.STORE_F16}[args.storage]
+    storage = args.storage or "f32"
+    second = None if args.storage or not args.workload.startswith("dense") else "f16"
     wl = make_workload(args.workload, args.seed)
-    cfg = _gpu_params(wl, storage)
-    cfg.overlap = args.overlap
-    if args.map_kernel is not None:
-        cfg.map_kernel = args.map_kernel
     dev = torch.device("cuda:0")
-    dom = L.Domain(cfg, device=dev)
-    dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
-    if wl.ramp:
-        r = wl.ramp
-        dom.set_mode(0, L.PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
-    print(f"[bench] workload {wl.name} lattice {cfg.nx}x{cfg.ny}x{cfg.nz} spheres {len(wl.R)} "
-          f"storage {args.storage}", file=sys.stderr, flush=True)
-
-    dom.step(args.warmup)
-    dom.sync()
-    if args.copy_probe_mib:
-        nb = args.copy_probe_mib << 20
-        a = torch.empty(nb, dtype=torch.uint8, device=dev)
-        b = torch.empty(nb, dtype=torch.uint8, device=dev)
-        for _ in range(3):
-            L.device_copy(b, a, nb, dom.stream)
-        torch.cuda.synchronize()
-    # timed region: HIP events around every sweep launch only (level 1)
-    dom.set_profiling(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dom.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dom.sync()
-    elapsed = t1 - t0
-    sweep_ms, sweep_n = dom.profile(0)
-    # per-kernel-group breakdown from a short extra run with every group timed
-    dom.set_profiling(2)
-    dom.step(min(args.steps, 100))
-    dom.sync()
-    brk = {k: dom.profile(j) for j, k in enumerate(("sweep", "dem_claims", "recon_commit_bc"))}
-    dom.set_profiling(0)
-    ncell = cfg.nx * cfg.ny * cfg.nz
-    flags = dom.field("flags")
-    nfluid = int((flags <= 1).sum())
-    mlups = ncell * args.steps / elapsed / 1e6
-    sweep_avg_s = sweep_ms / max(sweep_n, 1) / 1e3
-    bytes_per_launch = dom.sweep_bytes()
-    achieved = bytes_per_launch / sweep_avg_s / 1e9
-    s0 = dom.sphere(0)
-    traffic, traffic_src = traffic_record(args.workload, args.storage)
+    main_run = run_domain(wl, storage, args, dev)
+    other = run_domain(wl, second, args, dev, profile_breakdown=False) if second else None
+    cfg = main_run["cfg"]
+    achieved = main_run["bytes_per_step"] / main_run["sweep_avg_s"] / 1e9
+    coupled = main_run["bytes_per_step"] / (main_run["ms_per_step"] / 1e3) / 1e9
+    traffic, traffic_src = traffic_record(args.workload, storage)
 
     result = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(main_run["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "ms_per_step": round(main_run["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16"}[args.storage],
+        "dtype": storage,
         "data": "synthetic",
         "config": {
             "workload": f"{wl.name} {cfg.nx}x{cfg.ny}x{cfg.nz}, {len(wl.R)} sphere(s) D={2 * wl.R[0]:g}, "
-                        f"{args.storage.upper()} population storage",
+                        f"{storage.upper()} population storage",
             "lattice": [cfg.nx, cfg.ny, cfg.nz],
             "spheres": len(wl.R),
             "n_sub": cfg.n_sub,
             "collision": "TRT+aB",
             "seed": args.seed,
             "overlap": bool(args.overlap),
+            "map_kernel": cfg.map_kernel,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -363,33 +422,46 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "traffic_source": traffic_src,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": round(sweep_avg_s * 1e6, 3),
+            "bytes_per_launch": main_run["bytes_per_step"],
+            "avg_launch_us": round(main_run["sweep_avg_s"] * 1e6, 3),
         },
-        "mflups_fluid": round(nfluid * args.steps / elapsed / 1e6, 2),
-        "kernel_avg_us": {k: round(ms / max(n, 1) * 1e3, 3) for k, (ms, n) in brk.items()},
-        "sphere_final": {"z": float(s0["x"][2]), "uz": float(s0["u"][2]), "mode": s0["mode"]},
+        "coupled_step": {
+            "bytes_per_step": main_run["bytes_per_step"],
+            "achieved_GBps": round(coupled, 1),
+            "frac": round(coupled / HBM_PEAK_GBS, 4),
+        },
+        "mflups_fluid": round(main_run["mflups_fluid"], 2),
+        "kernel_avg_us": main_run["breakdown"],
+        "sphere_final": main_run["sphere0"],
     }
+    if other:
+        o_coupled = other["bytes_per_step"] / (other["ms_per_step"] / 1e3) / 1e9
+        o_sweep = other["bytes_per_step"] / other["sweep_avg_s"] / 1e9
+        result[f"{second}_form"] = {
+            "MLUPS": round(other["mlups"], 2), "ms_per_step": round(other["ms_per_step"], 5),
+            "sweep_GBps": round(o_sweep, 1), "sweep_frac": round(o_sweep / HBM_PEAK_GBS, 4),
+            "coupled_GBps": round(o_coupled, 1), "coupled_frac": round(o_coupled / HBM_PEAK_GBS, 4),
+            "bytes_per_step": other["bytes_per_step"],
+        }
     if wl.meta:
         result["config"]["params"] = {k: (round(v, 6) if isinstance(v, float) else v)
                                       for k, v in wl.meta.items()}
     if not args.no_cpu_baseline:
+        import oracle
+
         swl, what = cpu_sample(args.workload, wl, args.seed)
-        mlups_cpu, dt = cpu_baseline(swl, args.cpu_steps)
+        steps = args.cpu_steps or (15 if args.workload.startswith("dense") else 8)
+        mlups_cpu, dt, core = cpu_baseline(swl, steps)
         sn = (swl.params["nx"], swl.params["ny"], swl.params["nz"])
-        try:
-            cpu = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
-            model = [l.split(":", 1)[1].strip() for l in cpu.splitlines() if "Model name" in l][:1]
-        except Exception:
-            model = []
         result["cpu_baseline"] = {
             "value": round(mlups_cpu, 4),
             "unit": "MLUPS",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"{args.cpu_steps} coupled steps of {what} ({sn[0]}x{sn[1]}x{sn[2]}) from its "
-                      f"initial state ({dt:.1f} s, single thread)",
-            "cpu": model[0] if model else platform.processor(),
+            "sample": f"{steps} coupled steps of {what} ({sn[0]}x{sn[1]}x{sn[2]}) from its initial state "
+                      f"({dt:.1f} s, one thread pinned to host core {core})",
+            "cpu": cpu_model(),
+            "build": "gcc " + " ".join(oracle.BUILD_FLAGS),
         }
     print(json.dumps(result))
 

@@ -28,11 +28,13 @@ MODE_FREE, MODE_PRESCRIBED, MODE_FIXED = 0, 1, 2
 TRT_AB, TRT_B, TRT, SRT = 0, 1, 2, 3
 
 
+BUILD_FLAGS = ["-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, plain -O2)."""
     if force or not os.path.exists(_SO):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
-               "-o", _SO, _SRC, "-lm"]
+        cmd = ["gcc"] + BUILD_FLAGS + ["-o", _SO, _SRC, "-lm"]
         subprocess.check_call(cmd)
     return _SO
 

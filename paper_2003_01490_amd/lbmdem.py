@@ -7,9 +7,12 @@ missing this module raises at import of ``lib()``.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import sys
+import weakref
 
 import numpy as np
 
@@ -56,6 +59,21 @@ class Config(C.Structure):
 
 
 _lib = None
+
+# Domains and batches still open.  They are closed by an exit handler, which
+# runs before the HIP runtime tears down (a handle destroyed from a finaliser
+# during interpreter shutdown could reach a runtime that is already gone), and
+# a finaliser that runs during shutdown leaves the handle alone.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -177,6 +195,7 @@ class Domain:
         if rc != OK:
             raise LbmdemError(rc, lib().lbmdem_last_error(None).decode())
         self.h = h
+        _live.add(self)
 
     def _check(self, rc):
         if rc != OK:
@@ -189,6 +208,8 @@ class Domain:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -360,6 +381,7 @@ class Batch:
         if rc != OK:
             raise LbmdemError(rc, "batch creation failed")
         self.h = h
+        _live.add(self)
         self.stream = stream
         self.members = {}
         if not use_graph:
@@ -417,6 +439,8 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
