@@ -138,7 +138,9 @@ int32_t lbmdem_config_init(lbmdem_config* cfg);
  * Pure; makes no device call.  Returns 0 for an invalid configuration. */
 size_t lbmdem_footprint_bytes(const lbmdem_config* cfg);
 
-/* Creates a domain: fluid at rest (rho = 1, u = 0), no spheres.  dev_buf is a
+/* Creates a domain (Sec. 2.1: the D3Q19 lattice with walls and periodic
+ * sides; Alg. 1 starts from it): fluid at rest (rho = 1, u = 0, i.e. every
+ * population at its weight w_q), no spheres.  dev_buf is a
  * device region of at least lbmdem_footprint_bytes(cfg) bytes, 256-byte
  * aligned, owned by the caller (NULL: the library allocates one).  hip_stream
  * is a hipStream_t (NULL: the null stream).  *out receives the handle. */
@@ -148,8 +150,10 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
 /* Releases host resources and any library-owned device region.  Null-safe. */
 int32_t lbmdem_destroy(lbmdem_domain* dom);
 
-/* Adds n spheres (host arrays of 3n positions, velocities, angular
- * velocities; n radii and densities), borrowed for the call.  ids_out (may be
+/* Adds n spheres (Sec. 3: position, translational and angular velocity,
+ * radius, density; mass and moment of inertia of a solid sphere) from host
+ * arrays of 3n positions, velocities, angular velocities and n radii and
+ * densities, borrowed for the call.  ids_out (may be
  * NULL) receives their ids, which are dense and stable.  Returns
  * LBMDEM_EOVERLAP if a sphere crosses a wall plane or overlaps another sphere,
  * LBMDEM_ECAPACITY beyond max_spheres, LBMDEM_EINVAL if R > max_radius.
@@ -159,8 +163,9 @@ int32_t lbmdem_add_spheres(lbmdem_domain* dom, int32_t n, const double* x,
                            const double* rho, int32_t* ids_out);
 
 /* Overwrites positions (mask bit 0), velocities (bit 1), angular velocities
- * (bit 2) of n spheres between steps and re-maps them (uncovered cells are
- * reconstructed).  Host arrays, 3 doubles per sphere. */
+ * (bit 2) of n spheres between steps and re-maps them (the mapping of Sec.
+ * 2.2; uncovered cells are reconstructed by Eq. PDF_reconstruction).  Host
+ * arrays, 3 doubles per sphere. */
 int32_t lbmdem_update_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids,
                               const double* x, const double* u, const double* w,
                               int32_t mask);
@@ -174,8 +179,8 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode,
                                const double* u_target, double c_acc, double t_st,
                                double release_gap);
 
-/* Enqueues nsteps coupled time steps on the domain's stream; returns without
- * waiting. */
+/* Enqueues nsteps coupled time steps (Alg. 1 each) on the domain's stream;
+ * returns without waiting. */
 int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps);
 
 /* Waits for the domain's stream and reports device-side failures
@@ -185,21 +190,25 @@ int32_t lbmdem_sync(lbmdem_domain* dom);
 /* Number of spheres added so far. */
 int32_t lbmdem_num_spheres(const lbmdem_domain* dom);
 
-/* Synchronising copy of the state of sphere `id` into out[42] (host):
+/* Synchronising copy of the state of sphere `id` (quantities of App. B and
+ * Secs. 2.2, 3.1, 4.1.2, 4.2) into out[42] (host):
  *  0 x  3 u  6 w  9 F_fp 12 T_fp (averaged resolved hydrodynamic force/torque)
  * 15 F_tot 18 T_tot (total of the last sub-step) 21 F_lub 24 T_lub 27 F_col
  * 30 T_col 33 mode 34 R 35 rho 36 F_raw 39 T_raw (resolved, not averaged). */
 int32_t lbmdem_get_sphere_state(lbmdem_domain* dom, int32_t id, double* out);
 
-/* Synchronising copy of the states of n spheres (ids[s], or sphere s when ids
- * is NULL) into host arrays of 3n doubles each: positions, velocities,
+/* Synchronising copy of the states of n spheres (App. B quantities; ids[s],
+ * or sphere s when ids is NULL) into host arrays of 3n doubles each:
+ * positions, velocities,
  * angular velocities, averaged resolved force and torque (F_fp, T_fp of
  * Sec. 4.2) and total force and torque of the last sub-cycle.  Any output
  * pointer may be NULL to skip that quantity. */
 int32_t lbmdem_get_spheres(lbmdem_domain* dom, int32_t n, const int32_t* ids, double* x, double* u,
                            double* w, double* F_fp, double* T_fp, double* F_tot, double* T_tot);
 
-/* Synchronising copy of a whole-lattice field (LBMDEM_FIELD_*) to dst (host,
+/* Synchronising copy of a whole-lattice field (LBMDEM_FIELD_*: density and
+ * velocity are the moments of Sec. 2.1, flags and owners the mapping of Sec.
+ * 2.2) to dst (host,
  * or device when dst_is_device != 0) of `bytes` bytes; non-fluid cells read 0
  * in RHO, VEL and PDF. */
 int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t bytes,
@@ -226,7 +235,8 @@ int32_t lbmdem_probe_density(lbmdem_domain* dom, int32_t n, const double* xyz, d
  * or NULL arrays. */
 int32_t lbmdem_probe_density_static(lbmdem_domain* dom, int32_t n, const double* xyz, double* out);
 
-/* Overwrites all PDFs with the full distributions f (host, double[19N],
+/* Overwrites all PDFs (the post-collision state f~ of Eq. LBM_Collide) with
+ * the full distributions f (host, double[19N],
  * q-major), rounded to the storage precision, and recomputes the boundary
  * values of the next step. */
 int32_t lbmdem_set_pdf(lbmdem_domain* dom, const double* f);
@@ -257,6 +267,8 @@ int32_t lbmdem_set_stop_rule(lbmdem_domain* dom, int32_t rule, int64_t max_steps
 int32_t lbmdem_get_progress(lbmdem_domain* dom, int64_t* steps, int32_t* stopped);
 
 /* ---- batches: many domains advanced together (continuous batching) -------
+ * Not part of the paper's method: a serving layer that steps independent
+ * domains of the method (each one Alg. 1 per step) in shared launches.
  * A batch steps all its admitted domains with one launch per kernel kind
  * (fused stream-collide, DEM sub-cycles, claims, reconstruction, boundary
  * pass), replayed from a captured HIP graph.  Domains keep their state in

@@ -1042,11 +1042,13 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   __syncthreads();
 
   // 4. links: the listed cells in chunks of one cell per thread; a chunk's
-  // links (y, q) with y - c_q not this sphere's solid are listed in cell and
-  // direction order (ordered compaction), then shared out over all threads
+  // links (y, q) with y - c_q not this sphere's solid are listed direction by
+  // direction, cells in order within a direction (ordered compaction), then
+  // shared out over all threads: a wavefront's loads then walk neighbouring
+  // cells of one PDF plane, so the uses of a line come close together
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int nl = base;  // the same in every thread
-  __shared__ int wsum[4];
+  __shared__ int qcnt[Q][4];
   for (int c0 = 0; c0 < nl; c0 += blockDim.x) {
     const int e = c0 + threadIdx.x;
     uint32_t mask = 0u;
@@ -1057,22 +1059,25 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
       for (int q = 1; q < Q; ++q)
         if (st[t - CX[q] - he * (CY[q] + he * CZ[q])] != L_OWN) mask |= 1u << q;
     }
-    const int cnt = __popc(mask);
-    int v = cnt;  // inclusive scan over the wavefront
-    for (int o = 1; o < 64; o <<= 1) {
-      const int w = __shfl_up(v, o, 64);
-      if (lane >= o) v += w;
-    }
-    if (lane == 63) wsum[wid] = v;
-    __syncthreads();
-    int off = v - cnt, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-      if (w < wid) off += wsum[w];
-      tot += wsum[w];
-    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long bq[Q];
 #pragma unroll
-    for (int q = 1; q < Q; ++q)
-      if (mask & (1u << q)) lk[off++] = link_entry(t, q);
+    for (int q = 1; q < Q; ++q) {
+      bq[q] = __ballot((mask >> q) & 1u);
+      if (lane == 0) qcnt[q][wid] = __popcll(bq[q]);
+    }
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      int pre = 0, all = 0;
+      for (int w = 0; w < nw; ++w) {
+        if (w < wid) pre += qcnt[q][w];
+        all += qcnt[q][w];
+      }
+      if (mask & (1u << q)) lk[tot + pre + __popcll(bq[q] & below)] = link_entry(t, q);
+      tot += all;
+    }
     __syncthreads();
     for (int k0 = threadIdx.x; k0 < tot; k0 += BALL_LINK_UNROLL * blockDim.x)
       ball_links<T, BALL_LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
