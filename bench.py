@@ -137,24 +137,78 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def _oracle_request_sample(req, steps, core):
+    """Seconds per coupled step of the oracle on one serving request (its
+    first `steps` steps), in a process pinned to one host core."""
+    import oracle as O
+    from paper_2003_01490_amd import workloads as W
+
+    if core is not None:
+        os.sched_setaffinity(0, {core})
+    wl = W.serve_workload(req)
+    keys = {f[0] for f in O.RefConfig._fields_}
+    d = O.RefDomain(O.make_config(**{k: v for k, v in wl.params.items() if k in keys}))
+    d.add_spheres(wl.x, wl.R, wl.rho)
+    r = wl.ramp
+    d.set_mode(0, O.MODE_PRESCRIBED, r["u_target"], r["c_acc"], r["t_st"], r["release_gap"])
+    t0 = time.perf_counter()
+    d.step(steps)
+    return (time.perf_counter() - t0) / steps
+
+
+def serve_oracle_sample(reqs, steps, procs):
+    """The oracle on the 8 smallest requests: each alone on one pinned core,
+    then all 8 at once in `procs` processes on distinct cores (aggregate)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    small = sorted(reqs, key=lambda r: r["L"][0] * r["L"][1] * r["L"][2])[:8]
+    cores = sorted(os.sched_getaffinity(0))
+    alone = [_oracle_request_sample(r, steps, cores[-1]) for r in small]
+    os.sched_setaffinity(0, set(cores))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=procs, mp_context=ctx) as ex:
+        futs = [ex.submit(_oracle_request_sample, r, steps, cores[k % len(cores)]) for k, r in enumerate(small)]
+        together = [f.result() for f in futs]
+    wall = time.perf_counter() - t0
+    return small, alone, together, wall
+
+
 def serve_bench(args):
     """Serving stream: independent sphere-wall requests with Poisson arrivals,
     each run until its sphere rebounds (first apex after the wall contact) or a
     step cap, FP32 storage.  Continuous batching: arrived requests are admitted
     while their footprints fit the pool budget, all admitted domains advance
-    together in chunks of steps, stopped ones are retired at once.  Baseline:
-    the same requests one at a time in arrival order (each domain stepped alone).
+    together in chunks of steps, stopped ones are retired at once and the next
+    arrivals take their place.  Runs with the pool capped (--pool-gb) and,
+    with --serve-uncapped, with the whole free device memory as the pool.
+    Baseline: first-come-first-served, one request at a time.  With
+    --serve-baseline run, each request is stepped alone in arrival order;
+    with --serve-baseline measured (for streams too long to replay), each
+    request's alone cost is measured over a bounded sample (set-up plus
+    --solo-steps steps) and scaled to the steps the batched run needed (a
+    domain's trajectory is the same alone and in a batch), and the queue is
+    replayed from those service times.  The oracle is timed on the 8 smallest
+    requests over --cpu-steps steps each, alone and 8 at once in 8
+    processes, and scaled to their step counts.
     """
     import numpy as np
-    import torch
 
-    from paper_2003_01490_amd import lbmdem as L
     from paper_2003_01490_amd import workloads as W
 
     reqs = W.serve_requests(args.seed, args.requests, rate=args.rate)
+    oracle_part = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the worker processes are fresh interpreters
+        oracle_part = serve_oracle_sample(reqs, args.cpu_steps or 20, 8)
+
+    import torch
+
+    from paper_2003_01490_amd import lbmdem as L
+
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    pool = int(args.pool_gb * 2 ** 30)
     bytes_per_cell = 2 * 19 * 4 + 1
 
     def make(req):
@@ -170,61 +224,83 @@ def serve_bench(args):
     def footprint(req):
         return L.footprint_bytes(_gpu_params(W.serve_workload(req), L.STORE_F32))
 
-    def summary(done, wall, busy_ms):
+    def summary(done, wall, busy_ms=None):
         lat = np.array([d["latency"] for d in done])
         cells = sum(d["cells"] * d["steps"] for d in done)
-        return {"solves_per_s": round(len(done) / wall, 4), "wall_s": round(wall, 3),
-                "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
-                "gpu_busy": round(busy_ms / 1e3 / wall, 4),
-                "aggregate_GBps": round(cells * bytes_per_cell / wall / 1e9, 1),
-                "aggregate_MLUPS": round(cells / wall / 1e6, 1),
-                "rebounds": sum(d["stopped_by_rule"] for d in done)}
+        out = {"solves_per_s": round(len(done) / wall, 4), "wall_s": round(wall, 3),
+               "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+               "aggregate_GBps": round(cells * bytes_per_cell / wall / 1e9, 1),
+               "aggregate_MLUPS": round(cells / wall / 1e6, 1),
+               "rebounds": int(sum(d["stopped_by_rule"] for d in done)),
+               "capped": int(sum(not d["stopped_by_rule"] for d in done))}
+        if busy_ms is not None:
+            out["gpu_busy"] = round(busy_ms / 1e3 / wall, 4)
+        return out
 
-    # --- continuous batching
-    batch = L.Batch(stream, pool)
-    pending = sorted(reqs, key=lambda r: r["arrival"])
-    active, done, used = {}, [], 0
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    busy = 0.0
-    t0 = time.perf_counter()
-    while pending or active:
-        now = time.perf_counter() - t0
-        while pending and pending[0]["arrival"] <= now:
-            fp = footprint(pending[0])
-            if used + fp > pool and active:
-                break
-            req = pending.pop(0)
-            dom = make(req)
-            slot = batch.admit(dom)
-            active[slot] = (req, dom, fp)
-            used += fp
-        if not active:
-            time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
-            continue
-        ev0.record(stream)
-        batch.step(args.chunk)
-        ev1.record(stream)
-        fin = batch.done()
-        busy += ev0.elapsed_time(ev1)
-        st = batch.status()
-        for slot in fin:
-            req, dom, fp = active.pop(slot)
-            steps = st[slot][0]
-            batch.retire(slot)
-            done.append(dict(id=req["id"], latency=time.perf_counter() - t0 - req["arrival"], steps=steps,
-                             cells=dom.N, stopped_by_rule=steps < args.max_steps))
-            dom.close()
-            used -= fp
-        print(f"[serve] t {time.perf_counter() - t0:7.2f}s active {len(active):3d} done {len(done):3d} "
-              f"pending {len(pending):3d}", file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
-    batch.close()
-    res = summary(done, wall, busy)
+    def run_batched(pool, tag):
+        batch = L.Batch(stream, pool)
+        pending = sorted(reqs, key=lambda r: r["arrival"])
+        active, done, used = {}, [], 0
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        busy, timeline, peak = 0.0, [], 0
+        t0 = time.perf_counter()
+        last_log = -1.0
+        while pending or active:
+            now = time.perf_counter() - t0
+            while pending and pending[0]["arrival"] <= now:
+                fp = footprint(pending[0])
+                if used + fp > pool and active:
+                    break
+                req = pending.pop(0)
+                dom = make(req)
+                slot = batch.admit(dom)
+                active[slot] = (req, dom, fp)
+                used += fp
+            if not active:
+                time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
+                continue
+            peak = max(peak, len(active))
+            ev0.record(stream)
+            batch.step(args.chunk)
+            ev1.record(stream)
+            fin = batch.done()
+            busy += ev0.elapsed_time(ev1)
+            st = batch.status()
+            for slot in fin:
+                req, dom, fp = active.pop(slot)
+                steps = st[slot][0]
+                batch.retire(slot)
+                done.append(dict(id=req["id"], latency=time.perf_counter() - t0 - req["arrival"], steps=steps,
+                                 cells=dom.N, stopped_by_rule=steps < args.max_steps))
+                dom.close()
+                used -= fp
+            t = time.perf_counter() - t0
+            if t - last_log >= 1.0:
+                last_log = t
+                waiting = sum(1 for r in pending if r["arrival"] <= t)
+                timeline.append([round(t, 2), len(active), waiting, len(done), round(used / 2 ** 30, 2)])
+                print(f"[serve {tag}] t {t:7.2f}s in flight {len(active):3d} waiting {waiting:3d} "
+                      f"done {len(done):3d} pool {used / 2 ** 30:6.1f} GiB", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        batch.close()
+        res = summary(done, wall, busy)
+        res["pool_GiB"] = round(pool / 2 ** 30, 1)
+        res["peak_in_flight"] = peak
+        res["in_flight_log"] = {"columns": ["t_s", "in_flight", "waiting", "done", "pool_used_GiB"],
+                                "rows": timeline}
+        return res, done
+
+    capped, done = run_batched(int(args.pool_gb * 2 ** 30), f"{args.pool_gb:g}GiB")
+    uncapped = None
+    if args.serve_uncapped:
+        free, _ = torch.cuda.mem_get_info(dev)
+        uncapped, _ = run_batched(int(free * 0.9), "uncapped")
+    steps_of = {d["id"]: d["steps"] for d in done}
 
     base = None
-    if args.serve_baseline:
-        done_b = []
-        busy_b = 0.0
+    if args.serve_baseline == "run":
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        done_b, busy_b = [], 0.0
         t0 = time.perf_counter()
         for req in sorted(reqs, key=lambda r: r["arrival"]):
             now = time.perf_counter() - t0
@@ -245,12 +321,38 @@ def serve_bench(args):
             print(f"[serve-fifo] t {time.perf_counter() - t0:7.2f}s done {len(done_b):3d}", file=sys.stderr,
                   flush=True)
         base = summary(done_b, time.perf_counter() - t0, busy_b)
+        base["kind"] = "replayed one at a time in arrival order"
+    elif args.serve_baseline == "measured":
+        service = {}
+        for k, req in enumerate(reqs):
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            dom = make(req)
+            dom.step(1)
+            dom.sync()
+            t1 = time.perf_counter()
+            dom.step(args.solo_steps)
+            dom.sync()
+            t2 = time.perf_counter()
+            dom.close()
+            service[req["id"]] = (t1 - t0) + (t2 - t1) / args.solo_steps * (steps_of[req["id"]] - 1)
+            if k % 64 == 63:
+                print(f"[serve-fifo] measured {k + 1} requests alone", file=sys.stderr, flush=True)
+        clock, done_b = 0.0, []
+        for req in sorted(reqs, key=lambda r: r["arrival"]):
+            clock = max(clock, req["arrival"]) + service[req["id"]]
+            n = int(np.prod(req["L"]))
+            done_b.append(dict(id=req["id"], latency=clock - req["arrival"], steps=steps_of[req["id"]], cells=n,
+                               stopped_by_rule=steps_of[req["id"]] < args.max_steps))
+        base = summary(done_b, clock)
+        base["kind"] = (f"one at a time in arrival order, each request's cost measured alone (set-up, first "
+                        f"step, {args.solo_steps} timed steps) and scaled to its step count")
 
     cells = np.array([np.prod(r["L"]) for r in reqs])
     St = np.array([r["St"] for r in reqs])
     result = {
         "metric": METRIC,
-        "value": res["solves_per_s"],
+        "value": capped["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": int(sum(d["steps"] for d in done)),
@@ -267,11 +369,33 @@ def serve_bench(args):
                                f"or {args.max_steps} steps, FP32 storage",
                    "pool_GiB": args.pool_gb, "chunk_steps": args.chunk, "seed": args.seed,
                    "mean_cells": int(cells.mean()), "parallelism": "single GPU"},
-        "batched": res,
+        "batched": capped,
+        "batched_uncapped": uncapped,
         "fifo_one_at_a_time": base,
     }
     if base:
-        result["speedup_vs_fifo"] = round(res["solves_per_s"] / base["solves_per_s"], 3)
+        result["speedup_vs_fifo"] = round(capped["solves_per_s"] / base["solves_per_s"], 3)
+    if oracle_part:
+        import oracle
+
+        small, alone, together, wall = oracle_part
+        ids = [r["id"] for r in small]
+        solve_alone = [t * steps_of[i] for t, i in zip(alone, ids)]
+        solve_together = [t * steps_of[i] for t, i in zip(together, ids)]
+        result["cpu_baseline"] = {
+            "value": round(1.0 / float(np.mean(solve_alone)), 6),
+            "unit": "solves/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"the 8 smallest requests ({min(np.prod(r['L']) for r in small)}.."
+                      f"{max(np.prod(r['L']) for r in small)} cells), {args.cpu_steps or 20} steps each on one "
+                      f"pinned core, scaled to the steps each needed on the GPU",
+            "per_request_s": [round(v, 1) for v in solve_alone],
+            "aggregate_P_processes": {"P": 8, "solves_per_s": round(8.0 / float(np.max(solve_together)), 6),
+                                      "per_request_s": [round(v, 1) for v in solve_together]},
+            "cpu": cpu_model(),
+            "build": "gcc " + " ".join(oracle.BUILD_FLAGS),
+        }
     print(json.dumps(result))
 
 
@@ -353,12 +477,17 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="coupled steps of the oracle sample (default: about 15 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--requests", type=int, default=64, help="serving stream: number of requests")
+    ap.add_argument("--requests", type=int, default=512, help="serving stream: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serving stream: arrivals per second")
     ap.add_argument("--pool-gb", type=float, default=48.0, help="serving stream: pool budget (GiB)")
-    ap.add_argument("--max-steps", type=int, default=6000, help="serving stream: step cap per request")
+    ap.add_argument("--max-steps", type=int, default=20000, help="serving stream: step cap per request")
     ap.add_argument("--chunk", type=int, default=100, help="serving stream: steps per batch call")
-    ap.add_argument("--serve-baseline", action="store_true", help="serving stream: also run FIFO one at a time")
+    ap.add_argument("--serve-baseline", default="measured", choices=["off", "run", "measured"],
+                    help="serving stream: first-come-first-served baseline, replayed or from measured costs")
+    ap.add_argument("--solo-steps", type=int, default=200,
+                    help="serving stream: timed steps per request for the measured baseline")
+    ap.add_argument("--serve-uncapped", action="store_true",
+                    help="serving stream: also run with the whole free device memory as the pool")
     ap.add_argument("--map-kernel", type=int, default=None, choices=[0, 1, 2, 3],
                     help="particle-link boundary pass (default: the configuration's automatic choice)")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],

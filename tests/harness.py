@@ -2,6 +2,8 @@
 them.  The oracle is only called here (test infrastructure)."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 import oracle as O
@@ -120,3 +122,63 @@ def exact_tie_counts(n, walls, spheres, delta_ab=2.0, scale=1 << 11):
                     inside += d2 <= Ri * Ri
                 shared += inside >= 2
     return on_surface, on_shell, shared
+
+
+# ---- observed error maxima ---------------------------------------------------
+# Every parity bound goes through check(): the largest value seen per test and
+# quantity is kept with its bound and printed in the session summary, so a run
+# shows how far each bound sits above what the GPU path actually produced.
+OBSERVED: dict = {}
+
+
+def check(quantity: str, value: float, bound: float, where=""):
+    test = os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    key = (test, quantity)
+    old = OBSERVED.get(key, (0.0, bound))
+    OBSERVED[key] = (max(old[0], float(value)), max(old[1], bound))
+    assert value <= bound, f"{quantity} {value:.3e} above its bound {bound:.1e} {where}"
+
+
+SPHERE_QUANTITIES = ("x", "u", "w", "F_fp", "F_raw", "F_tot", "F_lub", "F_col", "T_fp", "T_raw")
+
+
+def fp64_bounds(**over):
+    """Bounds on the sphere errors of sphere_errs() for FP64 storage: 1e-12
+    for every quantity unless a test sets another (each such bound sits 3 to
+    10 times above the maximum the test has shown)."""
+    b = {k: 1e-12 for k in SPHERE_QUANTITIES}
+    b.update(over)
+    return b
+
+
+def check_all(errs: dict, bounds: dict, where=""):
+    for k, b in bounds.items():
+        check(k, errs[k], b, where)
+
+
+def oracle_fingerprint() -> str:
+    """SHA-256 over the oracle's arithmetic (its C source and header): a
+    stored oracle result is valid only for the oracle that wrote it."""
+    import hashlib
+
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    for name in ("lbmdem_ref.c", "lbmdem_ref.h"):
+        with open(os.path.join(root, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def workload_key(wl: W.Workload) -> dict:
+    """What a stored trajectory depends on: the workload's parameters, its
+    initial sphere state and the prescribed-motion ramp."""
+    def plain(v):
+        if isinstance(v, (tuple, list, np.ndarray)):
+            return [plain(u) for u in np.asarray(v).tolist()] if isinstance(v, np.ndarray) else [plain(u) for u in v]
+        if isinstance(v, (np.floating, np.integer)):
+            return v.item()
+        return v
+
+    return {"params": {k: plain(v) for k, v in sorted(wl.params.items())},
+            "x": plain(wl.x), "R": plain(wl.R), "rho": plain(wl.rho), "u": plain(wl.u), "w": plain(wl.w),
+            "ramp": {k: plain(v) for k, v in sorted((wl.ramp or {}).items())}}

@@ -1,11 +1,18 @@
 """GPU (HIP library through the C-ABI) against the FP64 oracle.
 
-FP64 storage: f, rho and u within 1e-12 of max|f| (u is a sum of f c_q with
-cancellation, so its error is bounded in units of f; it is also held to 1e-9
-of max|u| against gross errors), positions within 1e-12 D, sphere velocities
-and forces within 1e-10 of the trajectory's largest |u| and |F|; cell flags
-and owners bit for bit.  Reduced storage (FP32, FP16 deviations from w_q): errors against the
-oracle are printed and held to the bounds stated in each test.
+FP64 storage: f, rho and u within 1e-12 of max|f|, positions within 1e-12 D,
+cell flags and owners bit for bit.  Sphere velocities, angular velocities,
+forces and torques within 1e-12 of the trajectory's largest |u| and |F|,
+except where a test states a larger bound: those quantities come from the
+momentum-exchange sum over thousands of links whose net value is 1e-3 to
+1e-5 of their absolute sum, so summing in another order leaves relative
+errors of ~1e-16 times that ratio; each larger bound sits 3 to 10 times above
+the largest error the test has shown.  The velocity field relative to its own
+max|u| (vel_rel, which divides f-level rounding by |u|/|f| ~ 1e-3) has such
+bounds as well.  Every bound goes through harness.check(), which prints the
+observed maxima at the end of the session.  Reduced storage (FP32, FP16
+deviations from w_q): errors against the oracle are printed and held to the
+bounds stated in each test.
 """
 import numpy as np
 import pytest
@@ -13,7 +20,8 @@ import pytest
 import oracle as O
 from paper_2003_01490_amd import workloads as W
 
-from harness import Scales, exact_tie_counts, gpu_domain, oracle_domain, random_pdf, sphere_errs, weight
+from harness import (Scales, check, check_all, exact_tie_counts, fp64_bounds, gpu_domain, oracle_domain, random_pdf,
+                     sphere_errs, weight)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +32,7 @@ def _case(msg):
     print(f"[case] {msg}", flush=True)
 
 
-def _compare_fields(g, o, tol=TOL):
+def _compare_fields(g, o, tol=TOL, vel_rel=1e-12):
     cg, og = g.flags()
     co, oo = o.flags()
     assert np.array_equal(cg, co), "flags differ"
@@ -43,8 +51,9 @@ def _compare_fields(g, o, tol=TOL):
     rel_u = float(np.abs(ug - uo).max() / max(np.abs(uo).max(), 1e-300))
     print("  field errors", errs, f"u rel {rel_u:.1e}", flush=True)
     for k, e in errs.items():
-        assert e <= tol, (k, e)
-    assert rel_u <= 1e-9 or np.abs(uo).max() == 0.0
+        check(k, e, tol)
+    if np.abs(uo).max() > 0.0:
+        check("vel_rel", rel_u, vel_rel)
 
 
 @pytest.mark.parametrize("coll", [O.TRT_AB, O.TRT_B, O.TRT, O.SRT])
@@ -99,7 +108,7 @@ def test_wide_rows(storage):
     bound = 12 * (2.0 ** -11 if storage == 2 else 17 * 2.0 ** -24) * dev
     print(f"  storage {storage} wide rows: max |df| {err:.2e}, max |f - w| {dev:.2e}, bound {bound:.2e}",
           flush=True)
-    assert err <= bound, (err, dev)
+    check("pdf", err, bound)
 
 
 @pytest.mark.parametrize("coll,mk", [(O.TRT_AB, 0), (O.TRT_B, 0), (O.SRT, 0), (O.TRT_AB, 3)])
@@ -120,7 +129,7 @@ def test_body_force_fluid_and_fixed_sphere(coll, mk):
     g.set_pdf(f)
     o.step(10)
     g.step(10)
-    _compare_fields(g, o)
+    _compare_fields(g, o, vel_rel=2e-11)
     wl.x, wl.R, wl.rho = np.array([[8.3, 6.1, 7.7]]), np.array([3.2]), np.array([1.0])
     wl.u, wl.w = np.zeros((1, 3)), np.zeros((1, 3))
     o, g = oracle_domain(wl), gpu_domain(wl, map_kernel=mk)
@@ -132,9 +141,9 @@ def test_body_force_fluid_and_fixed_sphere(coll, mk):
         g.step(15)
         so, sg = o.sphere(0), g.sphere(0)
         Fs = max(np.abs(so["F_raw"]).max(), 1e-300)
-        assert np.abs(sg["F_raw"] - so["F_raw"]).max() <= 1e-10 * Fs
-        assert np.abs(sg["T_raw"] - so["T_raw"]).max() <= 1e-10 * Fs * 3.2
-    _compare_fields(g, o)
+        check("F_raw", np.abs(sg["F_raw"] - so["F_raw"]).max() / Fs, 2e-11)
+        check("T_raw", np.abs(sg["T_raw"] - so["T_raw"]).max() / (Fs * 3.2), 1e-12)
+    _compare_fields(g, o, vel_rel=2e-11)
 
 
 def test_density_probe_against_oracle_field():
@@ -164,7 +173,7 @@ def test_density_probe_against_oracle_field():
             fluid = fluid and code[ii[2], ii[1], ii[0]] <= O.SHELL
             ref += w * rho[ii[2], ii[1], ii[0]]
         if fluid:
-            assert abs(v - ref) <= 1e-12, (p, v, ref)
+            check("rho", abs(v - ref), 1e-12, p)
         else:
             assert np.isnan(v), (p, v)
 
@@ -204,7 +213,7 @@ def test_walls_on_all_axes(mk):
     for i in range(2):
         e = sphere_errs(g.sphere(i), o.sphere(i), 2 * wl.R[i])
         print("  sphere", i, {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
-        assert max(e.values()) < 1e-10
+        check_all(e, fp64_bounds(u=1e-11, w=2e-12, F_fp=2e-11, F_raw=2e-11, F_tot=2e-11, F_lub=1e-11))
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
@@ -266,9 +275,9 @@ def test_fixed_sphere_forces_on_random_field(mk):
         for i in range(2):
             so, sg = o.sphere(i), g.sphere(i)
             scale = np.abs(so["F_raw"]).max()
-            assert np.abs(sg["F_raw"] - so["F_raw"]).max() <= TOL * scale, (step, i)
-            tscale = np.abs(so["T_raw"]).max()
-            assert np.abs(sg["T_raw"] - so["T_raw"]).max() <= TOL * max(tscale, scale)
+            check("F_raw", np.abs(sg["F_raw"] - so["F_raw"]).max() / scale, TOL, (step, i))
+            tscale = max(np.abs(so["T_raw"]).max(), scale)
+            check("T_raw", np.abs(sg["T_raw"] - so["T_raw"]).max() / tscale, TOL, (step, i))
     _compare_fields(g, o)
 
 
@@ -286,8 +295,9 @@ def test_settling_sphere_32_fp64(seed, mk):
         so = o.sphere(0)
         e = sphere_errs(g.sphere(0), so, 2 * wl.R[0], sc.update(so))
         print(f"  step {chk}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
-        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_fp"] < 1e-10 and e["w"] < 1e-10, e
-    _compare_fields(g, o)
+        check_all(e, fp64_bounds(u=1e-10, w=2e-12, F_fp=5e-11, F_raw=5e-11, F_tot=5e-11, T_fp=1e-12,
+                                 T_raw=2e-12))
+    _compare_fields(g, o, vel_rel=2e-10)
 
 
 @pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
@@ -314,12 +324,13 @@ def test_contact_variant_fp64(mk):
             e = sphere_errs(g.sphere(0), so, 2 * wl.R[0], scale)
             print(f"  step {chk} kernel {k + 1} gap {so['x'][2] - 1 - wl.R[0]:.4f}",
                   {kk: f"{v:.1e}" for kk, v in e.items()}, flush=True)
-            assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10 and e["F_lub"] < 1e-10, e
+            check_all(e, fp64_bounds(u=1e-11, w=2e-12, F_fp=2e-11, F_raw=2e-11, F_tot=1e-11, F_lub=2e-11,
+                                     T_raw=2e-12))
         a, b = gs[0].sphere(0), gs[1].sphere(0)
         assert all(np.array_equal(a[k], b[k]) for k in ("x", "u", "w", "F_tot", "T_tot")), "DEM kernels differ"
     assert saw_contact or saw_lub
     for g in gs:
-        _compare_fields(g, o)
+        _compare_fields(g, o, vel_rel=5e-11)
 
 
 @pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
@@ -349,10 +360,10 @@ def test_two_spheres_oblique_collision_fp64(mk):
                 e = sphere_errs(g.sphere(i), so, 8.0, scale)
                 print(f"  step {chk} sphere {i} kernel {k + 1}", {kk: f"{v:.1e}" for kk, v in e.items()},
                       flush=True)
-                assert e["x"] < TOL and e["u"] < 1e-10 and e["w"] < 1e-10 and e["F_col"] < 1e-10, (chk, i, e)
+                check_all(e, fp64_bounds(u=2e-12), (chk, i))
     assert saw
     for g in gs:
-        _compare_fields(g, o)
+        _compare_fields(g, o, vel_rel=1e-11)
 
 
 @pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
@@ -377,9 +388,9 @@ def test_prescribed_ramp_and_release(mk):
         assert sg["mode"] == so["mode"]
         e = sphere_errs(sg, so, 8.0, sc.update(so))
         print(f"  step {chk}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
-        assert e["x"] < TOL and e["u"] < 1e-10 and e["F_tot"] < 1e-10, (chk, e)
+        check_all(e, fp64_bounds(), chk)
     assert released
-    _compare_fields(g, o)
+    _compare_fields(g, o, vel_rel=5e-12)
 
 
 @pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
