@@ -290,11 +290,17 @@ def serve_bench(args):
                                 "rows": timeline}
         return res, done
 
-    capped, done = run_batched(int(args.pool_gb * 2 ** 30), f"{args.pool_gb:g}GiB")
-    uncapped = None
-    if args.serve_uncapped:
+    def whole_device():
         free, _ = torch.cuda.mem_get_info(dev)
-        uncapped, _ = run_batched(int(free * 0.9), "uncapped")
+        return int(free * 0.9)
+
+    if args.pool_gb > 0:
+        capped, done = run_batched(int(args.pool_gb * 2 ** 30), f"{args.pool_gb:g}GiB")
+    else:  # no budget: the whole free device memory
+        capped, done = run_batched(whole_device(), "uncapped")
+    uncapped = None
+    if args.serve_uncapped and args.pool_gb > 0:
+        uncapped, _ = run_batched(whole_device(), "uncapped")
     steps_of = {d["id"]: d["steps"] for d in done}
 
     base = None
@@ -367,7 +373,7 @@ def serve_bench(args):
                                f"{args.rate}/s, edges U{{48..192}}, D U[6,24], St logU[1,1000] "
                                f"(median {np.median(St):.1f}), rho_r U[1.5,8], u_s 0.02, stop at rebound "
                                f"or {args.max_steps} steps, FP32 storage",
-                   "pool_GiB": args.pool_gb, "chunk_steps": args.chunk, "seed": args.seed,
+                   "pool_GiB": capped["pool_GiB"], "chunk_steps": args.chunk, "seed": args.seed,
                    "mean_cells": int(cells.mean()), "parallelism": "single GPU"},
         "batched": capped,
         "batched_uncapped": uncapped,
@@ -412,8 +418,11 @@ def run_domain(wl, storage_name, args, dev, profile_breakdown=True):
     cfg.overlap = args.overlap
     if args.map_kernel is not None:
         cfg.map_kernel = args.map_kernel
-    dom = L.Domain(cfg, device=dev)
+    # step graphs need a stream of their own (not the null stream)
+    dom = L.Domain(cfg, device=dev, stream=torch.cuda.Stream(device=dev) if args.graph else None)
     try:
+        if args.graph:
+            dom.set_graph(True)
         dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
         if wl.ramp:
             r = wl.ramp
@@ -430,14 +439,20 @@ def run_domain(wl, storage_name, args, dev, profile_breakdown=True):
                 L.device_copy(b, a, nb, dom.stream)
             torch.cuda.synchronize()
             del a, b
-        # timed region: HIP events around every sweep launch only (level 1)
-        dom.set_profiling(1)
+        # timed region: HIP events around every sweep launch only (level 1);
+        # with step graphs the timed steps replay the graph untimed and the
+        # sweep is timed over as many further steps launched directly
+        dom.set_profiling(0 if args.graph else 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dom.step(args.steps)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         dom.sync()
+        if args.graph:
+            dom.set_profiling(1)
+            dom.step(args.steps)
+            dom.sync()
         sweep_ms, sweep_n = dom.profile(0)
         brk = {}
         if profile_breakdown:
@@ -479,7 +494,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=512, help="serving stream: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serving stream: arrivals per second")
-    ap.add_argument("--pool-gb", type=float, default=48.0, help="serving stream: pool budget (GiB)")
+    ap.add_argument("--pool-gb", type=float, default=48.0,
+                    help="serving stream: pool budget (GiB; 0: the whole free device memory)")
     ap.add_argument("--max-steps", type=int, default=20000, help="serving stream: step cap per request")
     ap.add_argument("--chunk", type=int, default=100, help="serving stream: steps per batch call")
     ap.add_argument("--serve-baseline", default="measured", choices=["off", "run", "measured"],
@@ -492,6 +508,8 @@ def main():
                     help="particle-link boundary pass (default: the configuration's automatic choice)")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="run the DEM beside the sweep on a second stream (1, default) or after it (0)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay one captured step graph per step (lbmdem_set_graph)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -539,6 +557,7 @@ def main():
             "collision": "TRT+aB",
             "seed": args.seed,
             "overlap": bool(args.overlap),
+            "step_graph": bool(args.graph),
             "map_kernel": cfg.map_kernel,
             "parallelism": "single GPU",
         },

@@ -183,8 +183,21 @@ int32_t lbmdem_set_sphere_mode(lbmdem_domain* dom, int32_t id, int32_t mode,
  * returns without waiting. */
 int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps);
 
-/* Waits for the domain's stream and reports device-side failures
- * (LBMDEM_EUNSTABLE, LBMDEM_ECAPACITY). */
+/* Step graphs (HIP graphs instead of per-kernel launches): with use_graph
+ * != 0, lbmdem_step captures the launches of one step (Alg. 1) into a graph
+ * on first use and replays it once per step; it is captured again when the
+ * sphere count or the presence of prescribed motion changes.  Results are
+ * identical to direct launches.  Needs a domain stream other than the null
+ * stream (LBMDEM_EINVAL otherwise); while kernel timing is enabled steps are
+ * launched directly.  Default 0. */
+int32_t lbmdem_set_graph(lbmdem_domain* dom, int32_t use_graph);
+
+/* Waits for the domain's stream and reports device-side failures:
+ * LBMDEM_EUNSTABLE for a non-finite particle state or a fluid density outside
+ * (0.5, 1.5) at one of up to 65536 sampled cells (the same cells on every
+ * call; checked before the wait), LBMDEM_ECAPACITY for exhausted slots.  The
+ * domain then stays failed (LBMDEM_ESTATE from later calls); other domains
+ * are not affected. */
 int32_t lbmdem_sync(lbmdem_domain* dom);
 
 /* Number of spheres added so far. */

@@ -1,7 +1,9 @@
 """Oracle of the four-way coupled LBM-DEM scheme (Rettinger & Ruede).
 
 TEST INFRASTRUCTURE ONLY.  A plain single-threaded FP64 C implementation of the
-paper's method (``lbmdem_ref.c``) plus this ctypes wrapper.  Only ``tests/``,
+paper's method (``lbmdem_ref.c``), the same oracle behind the argument lists of
+the GPU library's C interface (``lbmdem_ref_abi.c``: ``lbmdem_ref_*``), plus
+this ctypes wrapper.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may load it;
 the GPU library never imports, links or calls anything here.
 
@@ -19,6 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liblbmdem_ref.so")
 _SRC = os.path.join(_HERE, "lbmdem_ref.c")
+_SRCS = [_SRC, os.path.join(_HERE, "lbmdem_ref_abi.c")]
+_HDRS = [os.path.join(_HERE, "lbmdem_ref.h"), os.path.join(_HERE, "lbmdem_ref_abi.h")]
 
 NQ = 19
 SPHERE_OUT = 42
@@ -32,10 +36,14 @@ BUILD_FLAGS = ["-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-share
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, plain -O2)."""
+    """Compile the oracle with gcc (no FMA contraction, plain -O2) into a new
+    file that then replaces the library (a process that has the old one
+    loaded keeps it intact)."""
     if force or not os.path.exists(_SO):
-        cmd = ["gcc"] + BUILD_FLAGS + ["-o", _SO, _SRC, "-lm"]
+        tmp = f"{_SO}.{os.getpid()}.tmp"
+        cmd = ["gcc"] + BUILD_FLAGS + ["-o", tmp] + _SRCS + ["-lm"]
         subprocess.check_call(cmd)
+        os.replace(tmp, _SO)
     return _SO
 
 
@@ -64,8 +72,7 @@ def lib():
     global _lib
     if _lib is None:
         stale = (not os.path.exists(_SO) or
-                 os.path.getmtime(_SO) < max(os.path.getmtime(_SRC),
-                                             os.path.getmtime(_SRC[:-1] + "h")))
+                 os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in _SRCS + _HDRS))
         if stale:
             build(force=True)
         L = C.CDLL(_SO)

@@ -294,6 +294,12 @@ struct lbmdem_domain {
   // that fork it from and join it to the domain's stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // one captured step, replayed per step (lbmdem_set_graph); re-captured
+  // when the launches it holds change (sphere count, prescribed motion)
+  int use_graph = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_P = -1, g_presc = -1;
 };
 
 static int32_t fail(lbmdem_domain* dom, int32_t code, const std::string& msg) {
@@ -645,6 +651,8 @@ int32_t lbmdem_destroy(lbmdem_domain* dom) {
   (void)hipStreamSynchronize(dom->stream);
   harvest(dom);
   for (auto e : dom->spare) (void)hipEventDestroy(e);
+  if (dom->gexec) (void)hipGraphExecDestroy(dom->gexec);
+  if (dom->graph) (void)hipGraphDestroy(dom->graph);
   if (dom->side) (void)hipStreamDestroy(dom->side);
   if (dom->ev_fork) (void)hipEventDestroy(dom->ev_fork);
   if (dom->ev_join) (void)hipEventDestroy(dom->ev_join);
@@ -821,11 +829,16 @@ static int32_t ensure_side(lbmdem_domain* dom) {
   return LBMDEM_OK;
 }
 
-int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
-  if (!dom || nsteps < 0) return LBMDEM_EINVAL;
-  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
-  if (dom->batch) return fail(dom, LBMDEM_EINVAL, "domain is stepped by its batch");
-  dom->d.P = (int)dom->hR.size();
+static void drop_step_graph(lbmdem_domain* dom) {
+  if (dom->gexec) (void)hipGraphExecDestroy(dom->gexec);
+  if (dom->graph) (void)hipGraphDestroy(dom->graph);
+  dom->gexec = nullptr;
+  dom->graph = nullptr;
+  dom->g_P = dom->g_presc = -1;
+}
+
+// the launches of nsteps steps, enqueued directly
+static int32_t step_direct(lbmdem_domain* dom, int32_t nsteps) {
   hipStream_t s0 = dom->stream;
   if (dom->d.fused) {
     // Alg. 1 in order on one stream: the sweep with the link boundary values
@@ -906,14 +919,59 @@ int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
   return LBMDEM_OK;
 }
 
+int32_t lbmdem_step(lbmdem_domain* dom, int32_t nsteps) {
+  if (!dom || nsteps < 0) return LBMDEM_EINVAL;
+  if (dom->failed) return fail(dom, LBMDEM_ESTATE, "domain has failed");
+  if (dom->batch) return fail(dom, LBMDEM_EINVAL, "domain is stepped by its batch");
+  dom->d.P = (int)dom->hR.size();
+  if (!dom->use_graph || dom->prof != 0 || nsteps == 0) return step_direct(dom, nsteps);
+  // every kernel reads its step state (buffer parity, stamp, step count) from
+  // device memory, so one captured step serves every step
+  const int presc = dom->may_prescribe ? 1 : 0;
+  if (!dom->gexec || dom->g_P != dom->d.P || dom->g_presc != presc) {
+    drop_step_graph(dom);
+    if (overlap_step(dom))
+      if (int32_t rc = ensure_side(dom)) return rc;
+    HIPCHK(dom, hipStreamBeginCapture(dom->stream, hipStreamCaptureModeThreadLocal));
+    const int32_t rc = step_direct(dom, 1);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(dom->stream, &g);
+    if (rc != LBMDEM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      if (rc != LBMDEM_OK) return rc;
+      return fail(dom, LBMDEM_EDEVICE, std::string("step graph capture: ") + hipGetErrorString(e));
+    }
+    dom->graph = g;
+    HIPCHK(dom, hipGraphInstantiate(&dom->gexec, dom->graph, nullptr, nullptr, 0));
+    dom->g_P = dom->d.P;
+    dom->g_presc = presc;
+  }
+  for (int k = 0; k < nsteps; ++k) HIPCHK(dom, hipGraphLaunch(dom->gexec, dom->stream));
+  return LBMDEM_OK;
+}
+
+int32_t lbmdem_set_graph(lbmdem_domain* dom, int32_t use_graph) {
+  if (!dom) return LBMDEM_EINVAL;
+  if (use_graph && !dom->stream) return fail(dom, LBMDEM_EINVAL, "step graphs need a stream other than the null stream");
+  drop_step_graph(dom);
+  dom->use_graph = use_graph ? 1 : 0;
+  return LBMDEM_OK;
+}
+
 int32_t lbmdem_sync(lbmdem_domain* dom) {
   if (!dom) return LBMDEM_EINVAL;
+  if (!dom->failed) launch_density_check(dom->d, dom->stream);
   HIPCHK(dom, hipStreamSynchronize(dom->stream));
   int st = 0;
   HIPCHK(dom, hipMemcpy(&st, dom->d.status, 4, hipMemcpyDeviceToHost));
   if (st & ST_NONFINITE) {
     dom->failed = 1;
     return fail(dom, LBMDEM_EUNSTABLE, "non-finite particle state");
+  }
+  if (st & ST_DENSITY) {
+    dom->failed = 1;
+    return fail(dom, LBMDEM_EUNSTABLE, "a sampled fluid density left (0.5, 1.5)");
   }
   if (st & (ST_HIST_FULL | ST_NBR_FULL | ST_TILE_FULL)) {
     dom->failed = 1;

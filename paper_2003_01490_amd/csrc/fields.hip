@@ -160,6 +160,35 @@ void launch_probe_density(const DevDomain& d, double* io, int n, hipStream_t s) 
     hipLaunchKernelGGL(k_probe_density<__half>, g, dim3(256), 0, s, d, io, n);
 }
 
+// Health check of the fluid: the density 1 + sum_q g_q of up to
+// DENSITY_SAMPLES fluid cells spread over the lattice by a multiplicative
+// hash (the same cells on every call); one outside (0.5, 1.5), or not finite,
+// raises ST_DENSITY.
+constexpr int DENSITY_SAMPLES = 65536;
+template <typename T>
+__global__ void k_density_check(DevDomain d, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const size_t N = (size_t)d.N;
+  const size_t c = n == (int)N ? (size_t)k : (size_t)(((unsigned long long)k * 2654435761ull) % N);
+  if (d.flags[c] & (F_SOLID | F_WALL)) return;
+  const T* f = (const T*)(d.ctl->cur ? d.pdf[1] : d.pdf[0]);
+  double rho = 1.0;
+  for (int q = 0; q < Q; ++q) rho += to_d<T>(f[(size_t)q * N + c]);
+  if (!(rho > 0.5 && rho < 1.5)) atomicOr(d.status, ST_DENSITY);
+}
+
+void launch_density_check(const DevDomain& d, hipStream_t s) {
+  const int n = d.N < (long long)DENSITY_SAMPLES ? (int)d.N : DENSITY_SAMPLES;
+  const dim3 g((unsigned)((n + 255) / 256));
+  if (d.storage == 0)
+    hipLaunchKernelGGL(k_density_check<double>, g, dim3(256), 0, s, d, n);
+  else if (d.storage == 1)
+    hipLaunchKernelGGL(k_density_check<float>, g, dim3(256), 0, s, d, n);
+  else
+    hipLaunchKernelGGL(k_density_check<__half>, g, dim3(256), 0, s, d, n);
+}
+
 static dim3 grid_for(size_t n) {
   size_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;

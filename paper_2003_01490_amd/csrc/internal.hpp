@@ -40,6 +40,7 @@ constexpr int ST_NONFINITE = 1;
 constexpr int ST_HIST_FULL = 2;
 constexpr int ST_NBR_FULL = 4;
 constexpr int ST_TILE_FULL = 8;   // a fused-sweep tile met more spheres than its table holds
+constexpr int ST_DENSITY = 16;    // a sampled fluid density lies outside (0.5, 1.5) or is not finite
 
 constexpr int BIN_CAP = 15;      // sphere ids per neighbour-search bin (+1 count)
 
@@ -367,6 +368,7 @@ void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // fused step: the sweep with the particle links and momentum exchange, and
 // the per-sphere sums of its tile partials (into partial[i][6])
 void launch_sweep_fused(const DevDomain& d, hipStream_t s);
+void launch_density_check(const DevDomain& d, hipStream_t s);
 void launch_force_reduce(const DevDomain& d, hipStream_t s);
 // fused step after the DEM: mapping bins of the new positions, reconstruction,
 // flags and owners of the cells that change, step control

@@ -120,6 +120,7 @@ def lib():
         "lbmdem_batch_done": (C.c_int32, [vp, ip, ip]),
         "lbmdem_batch_last_error": (C.c_char_p, [vp]),
         "lbmdem_set_profiling": (C.c_int32, [vp, C.c_int32]),
+        "lbmdem_set_graph": (C.c_int32, [vp, C.c_int32]),
         "lbmdem_get_profile": (C.c_int32, [vp, C.c_int32, dp, C.POINTER(C.c_int64)]),
         "lbmdem_sweep_bytes": (C.c_double, [vp]),
         "lbmdem_probe_density": (C.c_int32, [vp, C.c_int32, dp, dp]),
@@ -354,6 +355,10 @@ class Domain:
     def set_pdf(self, f):
         f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(19 * self.N))
         self._check(lib().lbmdem_set_pdf(self.h, _dp(f)))
+
+    def set_graph(self, on: bool = True):
+        """Replay one captured step graph per step (needs a non-null stream)."""
+        self._check(lib().lbmdem_set_graph(self.h, 1 if on else 0))
 
     # --- profiling --------------------------------------------------------
     def set_profiling(self, level: int):

@@ -547,3 +547,120 @@ def test_unstable_state_is_reported_and_isolated():
     got = pair[0].spheres()
     assert all(np.array_equal(got[k], ref[k]) for k in ref), "the healthy domain was disturbed"
     b.close()
+
+
+def test_one_harness_drives_both_interfaces():
+    """The same ctypes code (tests/abi_harness.py) drives the GPU library's
+    lbmdem_* calls and the oracle's lbmdem_ref_* mirror: contact with the wall
+    and lubrication (contact_32, FP64 storage, 200 steps), sphere state and
+    fields compared as in test_contact_variant_fp64."""
+    from abi_harness import AbiDomain, config_from
+    from paper_2003_01490_amd import lbmdem as L
+
+    wl = W.contact_32(0)
+    _case("contact_32 FP64 through one harness: lbmdem_* against lbmdem_ref_*")
+    doms = []
+    for lib, prefix in ((L.lib(), "lbmdem_"), (O.lib(), "lbmdem_ref_")):
+        cfg = config_from(wl.params, lib, prefix, storage=0, max_radius=float(wl.R[0]),
+                          max_spheres=max(len(wl.R), 1))
+        dom = AbiDomain(lib, prefix, cfg)
+        dom.add_spheres(wl.x, wl.R, wl.rho, u=wl.u, w=wl.w)
+        doms.append(dom)
+    g, o = doms
+    sc = Scales(weight(wl))
+    done = 0
+    for chk in (20, 100, 200):
+        for dom in doms:
+            dom.step(chk - done)
+        done = chk
+        so = o.sphere(0)
+        e = sphere_errs(g.sphere(0), so, 2 * wl.R[0], sc.update(so))
+        print(f"  step {chk}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        check_all(e, fp64_bounds(u=1e-11, w=2e-12, F_fp=2e-11, F_raw=2e-11, F_tot=1e-11, F_lub=2e-11,
+                                 T_raw=2e-12), chk)
+    assert np.array_equal(g.field("flags"), o.field("flags"))
+    sol = o.field("flags") == O.SOLID
+    assert np.array_equal(g.field("owner")[sol], o.field("owner")[sol])
+    fo = o.field("pdf")
+    check("pdf", float(np.abs(g.field("pdf") - fo).max() / np.abs(fo).max()), TOL)
+    for dom in doms:
+        dom.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_density_out_of_range_is_reported(storage):
+    """The sampled density check of lbmdem_sync: a fluid at rho = 1.6 (set
+    from the host, a state no stable run reaches) is reported as
+    LBMDEM_EUNSTABLE and fails the domain; the same field at rho = 1.4 and a
+    domain beside the failed one stay healthy."""
+    from paper_2003_01490_amd import lbmdem as L
+
+    n = (24, 20, 18)
+    _case(f"density range check, storage {storage}")
+    wl = W.Workload("rho", W.base_params(nx=n[0], ny=n[1], nz=n[2], nu=0.05, max_spheres=1),
+                    np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), 0)
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None, None, None]
+    ok, bad = gpu_domain(wl, storage=storage), gpu_domain(wl, storage=storage)
+    ok.set_pdf(np.broadcast_to(1.4 * w, (19,) + n[::-1]))
+    bad.set_pdf(np.broadcast_to(1.6 * w, (19,) + n[::-1]))
+    for d in (ok, bad):
+        d.step(1)
+    ok.sync()
+    with pytest.raises(L.LbmdemError) as e:
+        bad.sync()
+    assert e.value.code == L.EUNSTABLE and "density" in str(e.value)
+    with pytest.raises(L.LbmdemError) as e:
+        bad.step(1)
+    assert e.value.code == L.ESTATE
+    ok.step(3)
+    ok.sync()
+    for d in (ok, bad):
+        d.close()
+
+
+@pytest.mark.parametrize("wlname,mk", [("contact", 0), ("dense", 0), ("dense", 3)])
+def test_step_graph_equals_direct_launches(wlname, mk):
+    """A domain stepped by replaying one captured step graph ends bit for bit
+    as one stepped by direct launches: through a wall contact (one sphere,
+    prescribed-free DEM, overlap of sweep and DEM on two streams) and in the
+    dense 96^3 suspension (many-sphere DEM chain; the fused step too), over
+    several replays with host reads between them, and across a re-capture
+    after a sphere is added."""
+    import torch
+    from paper_2003_01490_amd import lbmdem as L
+
+    wl = W.contact_32(0) if wlname == "contact" else W.dense(0, n=96, count=156)
+    _case(f"step graph against direct launches: {wlname}, map_kernel {mk}")
+    stream = torch.cuda.Stream()
+    extra = max(len(wl.R), 1) + 1
+    a = gpu_domain(wl, storage=1, stream=stream, map_kernel=mk, max_spheres=extra)
+    b = gpu_domain(wl, storage=1, stream=stream, map_kernel=mk, max_spheres=extra)
+    b.set_graph(True)
+    for chunk in (1, 7, 30):
+        a.step(chunk)
+        b.step(chunk)
+        sa, sb = a.spheres(), b.spheres()
+        assert all(np.array_equal(sa[k], sb[k]) for k in sa), f"spheres differ after a chunk of {chunk}"
+    R = 2.0
+    placed = None
+    for fx in np.linspace(0.1, 0.9, 9):
+        for fy in np.linspace(0.1, 0.9, 9):
+            x = np.array([[wl.params["nx"] * fx + 0.25, wl.params["ny"] * fy, wl.params["nz"] - 2.5 - R]])
+            try:
+                a.add_spheres(x, np.array([R]), np.array([2.0]))
+            except L.LbmdemError as e:
+                assert e.code == L.EOVERLAP
+                continue
+            placed = x
+            break
+        if placed is not None:
+            break
+    assert placed is not None, "no free place for the added sphere"
+    b.add_spheres(placed, np.array([R]), np.array([2.0]))
+    a.step(12)
+    b.step(12)
+    sa, sb = a.spheres(), b.spheres()
+    assert all(np.array_equal(sa[k], sb[k]) for k in sa), "spheres differ after the re-capture"
+    assert np.array_equal(a.field("pdf"), b.field("pdf"))
+    for d in (a, b):
+        d.close()
