@@ -89,8 +89,11 @@ static void launch_sweep_t(const DevDomain& d, hipStream_t s) {
     block.x = d.nx;
     block.y = d.nx <= 256 ? 256 / d.nx : 1;
   } else {
-    // 128 x 2 measured best for 384-wide rows
-    const int cand[4] = {128, 256, 192, 64};
+    // the widest piece of 256 or 128 cells that divides the row: 256 x 1 at
+    // 512^3 FP32 (3.80 against 3.99 ms alone with 128 x 2 and 4.00 ms with
+    // whole 512-cell rows), 128 x 2 for 384-wide rows (1.55 ms; whole rows
+    // 1.63 ms)
+    const int cand[4] = {256, 128, 192, 64};
     block.x = 256;
     for (int c : cand)
       if (d.nx % c == 0) {

@@ -1,0 +1,114 @@
+"""The sphere-wall collision on 128 x 128 x 256 cells (Sec. 4.4: D_p = 20,
+the St = 100 row of Tab. sphereWallCollision, prescribed approach at
+u_s = 0.028 by Eq. (artificial_acceleration) with c_acc = 10, released one
+diameter above the bottom wall; T_c and the lubrication cut-off from Eqs.
+(collisionTimeChoice) and (lubricationGapSize)), followed through approach,
+contact and rebound.
+
+* GPU FP64 against the FP64 oracle over the first 2,000 steps, at the steps
+  stored in tests/golden/sphere_wall_oracle_2000.json (written by the
+  oracle alone, keyed by the workload and the oracle's source hash).
+* GPU FP32 storage against GPU FP64 storage over the whole run, step by
+  step: the gap delta(t) = z - R - z_wall, the first and last step of wall
+  contact, the contact duration, the apparent restitution -u_z(out)/u_z(in)
+  at the contact boundaries, and the rebound height H_r of Eq.
+  (rebound_height), the largest gap after contact, in diameters.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2003_01490_amd import workloads as W
+
+from harness import Scales, check_all, fp64_bounds, gpu_domain, oracle_fingerprint, sphere_errs, weight, workload_key
+
+pytestmark = pytest.mark.gpu
+
+FIXTURE = os.path.join(os.path.dirname(__file__), "golden", "sphere_wall_oracle_2000.json")
+Z_WALL = 1.0  # half-way wall between the wall layer z = 0 and the first fluid layer
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def test_sphere_wall_fp64_matches_oracle_first_2000_steps():
+    wl = W.sphere_wall(0)
+    doc = json.load(open(FIXTURE))
+    assert doc["oracle_sha256"] == oracle_fingerprint(), \
+        "stored oracle run is stale: rerun tests/golden/make_sphere_wall_oracle.py"
+    assert doc["key"] == json.loads(json.dumps(workload_key(wl))), "stored oracle run is for another workload"
+    _case(f"sphere-wall 128x128x256 FP64 against {len(doc['records'])} stored oracle states, 2,000 steps")
+    g = gpu_domain(wl)
+    sc = Scales(weight(wl))
+    done = 0
+    for r in doc["records"]:
+        g.step(r["step"] - done)
+        done = r["step"]
+        so = {k: np.array(v) for k, v in r.items() if k not in ("step", "mode")}
+        sg = g.sphere(0)
+        assert int(sg["mode"]) == r["mode"], (r["step"], sg["mode"], r["mode"])
+        e = sphere_errs(sg, so, 2 * wl.R[0], sc.update(so))
+        if r["step"] in (1, 20, 500, 1000, 2000):
+            print(f"  step {r['step']} z {so['x'][2]:.6f}", {k: f"{v:.1e}" for k, v in e.items()}, flush=True)
+        check_all(e, fp64_bounds(u=1e-11, F_fp=1e-11, F_raw=1e-11, F_tot=1e-11, T_fp=1e-11, T_raw=1e-11,
+                                 w=1e-11), r["step"])
+    g.close()
+
+
+def _trajectory(storage, steps):
+    """Per-step gap and vertical velocity of the sphere-wall run, plus the
+    contact force's vertical component."""
+    wl = W.sphere_wall(0)
+    g = gpu_domain(wl, storage=storage)
+    R = wl.R[0]
+    gap, uz, fcol = np.empty(steps), np.empty(steps), np.empty(steps)
+    for k in range(steps):
+        g.step(1)
+        s = g.sphere(0)
+        gap[k] = s["x"][2] - R - Z_WALL
+        uz[k] = s["u"][2]
+        fcol[k] = s["F_col"][2]
+    g.close()
+    return gap, uz, fcol, 2 * R
+
+
+def _events(gap, uz, fcol, D):
+    """Contact start (first step with a contact force), contact end t_c (first
+    step after it without one), restitution -u_z(t_c) / u_z(start - 1) and
+    H_r = max gap / D over t > t_c (Eq. rebound_height)."""
+    on = np.nonzero(fcol != 0.0)[0]
+    assert len(on), "no contact"
+    t0 = int(on[0])
+    off = np.nonzero(fcol[t0:] == 0.0)[0]
+    assert len(off), "contact does not end"
+    tc = t0 + int(off[0])
+    after = gap[tc:]
+    apex = tc + int(np.argmax(after))
+    return {"t_contact": t0 + 1, "t_c": tc + 1, "duration": tc - t0, "u_in": float(uz[t0 - 1]),
+            "u_out": float(uz[tc]), "e": float(-uz[tc] / uz[t0 - 1]), "H_r": float(after.max() / D),
+            "t_apex": apex + 1, "min_gap": float(gap[t0:tc].min() / D)}
+
+
+@pytest.mark.timeout(600)
+def test_sphere_wall_fp32_against_fp64_through_rebound():
+    steps = 16000
+    _case(f"sphere-wall 128x128x256, FP64 and FP32 storage, {steps} steps step by step")
+    g64, u64, c64, D = _trajectory(0, steps)
+    g32, u32, c32, _ = _trajectory(1, steps)
+    e64, e32 = _events(g64, u64, c64, D), _events(g32, u32, c32, D)
+    for k in range(0, steps, 1000):
+        print(f"  step {k + 1:6d} gap/D FP64 {g64[k] / D:.6f} FP32 {g32[k] / D:.6f}", flush=True)
+    print("  FP64", {k: (f"{v:.6g}" if isinstance(v, float) else v) for k, v in e64.items()}, flush=True)
+    print("  FP32", {k: (f"{v:.6g}" if isinstance(v, float) else v) for k, v in e32.items()}, flush=True)
+    assert e64["t_apex"] < steps - 100 and g64[-1] < g64[e64["t_apex"] - 1], "the run must pass the first apex"
+    # the two storages agree to ~1e-5 D over the run (observed 1e-5 D, H_r and
+    # e to 6 digits): contact events to the step, e and H_r to 1e-4
+    assert e64["t_contact"] == e32["t_contact"] and abs(e64["duration"] - e32["duration"]) <= 1
+    assert abs(e64["e"] - e32["e"]) <= 1e-4 * abs(e64["e"])
+    assert abs(e64["H_r"] - e32["H_r"]) <= 1e-4 * e64["H_r"]
+    dz = np.abs(g64 - g32).max() / D
+    print(f"  max |gap FP32 - gap FP64| / D over the run: {dz:.2e}", flush=True)
+    assert dz <= 1e-4
