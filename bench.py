@@ -127,14 +127,33 @@ def cpu_baseline(wl, steps):
 
 
 def cpu_model() -> str:
+    """The host CPU: lscpu's model name, with family, model and stepping from
+    /proc/cpuinfo (a virtualised host may report only a generic name)."""
+    name = None
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
         for line in out.splitlines():
             if line.startswith("Model name"):
-                return line.split(":", 1)[1].strip()
+                name = line.split(":", 1)[1].strip()
+                break
     except Exception:
         pass
-    return platform.processor() or "unknown"
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" in line:
+                    k, v = (t.strip() for t in line.split(":", 1))
+                    if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                        info[k] = v
+                if not line.strip() and info:
+                    break
+    except OSError:
+        pass
+    name = name or info.get("model name") or platform.processor() or "unknown"
+    if "cpu family" in info:
+        name += f" (family {info['cpu family']}, model {info.get('model', '?')}, stepping {info.get('stepping', '?')})"
+    return name
 
 
 def _oracle_request_sample(req, steps, core):
