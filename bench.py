@@ -617,7 +617,7 @@ def main():
         import oracle
 
         swl, what = cpu_sample(args.workload, wl, args.seed)
-        steps = args.cpu_steps or (15 if args.workload.startswith("dense") else 8)
+        steps = args.cpu_steps or (20 if args.workload.startswith("dense") else 8)
         mlups_cpu, dt, core = cpu_baseline(swl, steps)
         sn = (swl.params["nx"], swl.params["ny"], swl.params["nz"])
         result["cpu_baseline"] = {
