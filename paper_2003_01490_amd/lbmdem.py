@@ -332,6 +332,15 @@ class Domain:
         self._check(lib().lbmdem_get_field(self.h, fid, C.c_void_p(out.ctypes.data), out.nbytes, 0))
         return out.reshape(shape)
 
+    def field_into(self, which: str, out) -> None:
+        """Synchronising copy of a whole-lattice field into the device tensor
+        `out` (float64 rho (N), vel (3N) or pdf (19N); uint8 flags; int32
+        owner), for fields too large to bring to the host."""
+        fid = {"rho": FIELD_RHO, "vel": FIELD_VEL, "pdf": FIELD_PDF, "flags": FIELD_FLAGS,
+               "owner": FIELD_OWNER}[which]
+        self._check(lib().lbmdem_get_field(self.h, fid, C.c_void_p(out.data_ptr()),
+                                           out.numel() * out.element_size(), 1))
+
     def flags(self):
         return self.field("flags"), self.field("owner")
 

@@ -243,3 +243,99 @@ def test_reduced_storage_128_against_fp64():
         ex = float(np.abs(s["x"] - s0["x"]).max() / 12.0)
         print(f"  storage {storage}: |du|/|u| {eu:.2e}  |dF|/|F| {ef:.2e}  |dx|/D {ex:.2e}", flush=True)
         assert eu <= tol_u and ef <= tol_f and ex <= tol_x
+
+
+@pytest.mark.timeout(600)
+def test_headline_512_sampled_against_oracle():
+    """The benchmark's headline configuration at full size (dense 512^3,
+    24,000 spheres D = 12, FP32 storage, automatic kernels, DEM beside the
+    sweep), where the oracle cannot run the whole lattice:
+    * closure of the momentum exchange in fluid at rest (step 1);
+    * 2,000 sampled fluid cells whose 18 neighbours are fluid: the values
+      they hold after step 11 against the oracle's collision operator applied
+      to the 19 values they pulled (read from the GPU field after step 10),
+      within 40 FP32 roundings of the largest deviation from w_q (the sweep
+      collides in FP32, the oracle in FP64 from the same inputs: about one
+      rounding per deviation summed into the moments and per relaxed term,
+      and the rounding of the stored result; 11.9 observed) plus 4e-15 for
+      the oracle's FP64 rounding on full f; shell cells (TRT+aB) included;
+    * the mapping of 20 sampled sphere boxes against the closed-ball rule."""
+    import torch
+    from paper_2003_01490_amd import lbmdem as L
+
+    wl = W.dense(0, n=512, count=24000, steps=1000)
+    P = len(wl.R)
+    n = (512, 512, 512)
+    N = n[0] * n[1] * n[2]
+    _case(f"dense 512^3, {P} spheres, FP32, bench configuration: closure, sampled collision, sampled mapping")
+    g = gpu_domain(wl, storage=L.STORE_F32)
+    g.step(1)
+    g.sync()
+    s = g.spheres()
+    fmax, tmax = float(np.abs(s["F_fp"]).max()), float(np.abs(s["T_fp"]).max())
+    print(f"  step 1: max |F_fp| {fmax:.2e}  max |T_fp| {tmax:.2e}", flush=True)
+    assert fmax < 1e-11 and tmax < 1e-10
+    g.step(9)
+    g.sync()
+    flags = g.field("flags")  # (z, y, x); 0 fluid, 1 shell, 2 solid, 3 wall
+    c, w, _ = O.lattice()
+    rng = np.random.default_rng(11)
+    cand = np.column_stack([rng.integers(0, n[0], 20000), rng.integers(0, n[1], 20000),
+                            rng.integers(2, n[2] - 2, 20000)])
+    ok = np.ones(len(cand), dtype=bool)
+    for q in range(19):
+        xs = (cand[:, 0] + c[q, 0]) % n[0]
+        ys = (cand[:, 1] + c[q, 1]) % n[1]
+        zs = cand[:, 2] + c[q, 2]
+        ok &= flags[zs, ys, xs] <= 1
+    cells = cand[ok][:2000]
+    assert len(cells) == 2000
+    idx = cells[:, 0] + n[0] * (cells[:, 1] + n[1] * cells[:, 2])
+    src = np.stack([((cells[:, 0] - c[q, 0]) % n[0]) + n[0] * (((cells[:, 1] - c[q, 1]) % n[1])
+                    + n[1] * (cells[:, 2] - c[q, 2])) + q * N for q in range(19)], axis=1)
+    dev = torch.device("cuda:0")
+    pdf = torch.empty(19 * N, dtype=torch.float64, device=dev)
+    g.field_into("pdf", pdf)
+    pulled = pdf[torch.from_numpy(src).to(dev)].cpu().numpy()
+    g.step(1)
+    g.field_into("pdf", pdf)
+    post = pdf[torch.from_numpy(np.stack([idx + q * N for q in range(19)], axis=1)).to(dev)].cpu().numpy()
+    del pdf
+    torch.cuda.empty_cache()
+    keys = {f[0] for f in O.RefConfig._fields_}
+    cfg = O.make_config(**{k: v for k, v in wl.params.items() if k in keys})
+    shell = flags[cells[:, 2], cells[:, 1], cells[:, 0]] == 1
+    # bound: 40 FP32 roundings of the largest deviation (the sweep) plus the
+    # oracle's own FP64 rounding on full f of order 1/3 (cells at rest carry
+    # no deviation at all)
+    worst, emax = 0.0, 0.0
+    for k in range(len(cells)):
+        ref = O.collide(cfg, pulled[k], shell=bool(shell[k]))
+        dev_k = float(np.abs(pulled[k] - w).max())
+        e = float(np.abs(post[k] - ref).max())
+        emax = max(emax, e)
+        worst = max(worst, (e - 4e-15) / max(dev_k * 2.0 ** -24, 1e-300))
+        assert e <= 40 * 2.0 ** -24 * dev_k + 4e-15, (k, cells[k], e, dev_k)
+    print(f"  {len(cells)} sampled cells ({int(shell.sum())} in shells): max error {emax:.2e}, at most "
+          f"{max(worst, 0.0):.2f} FP32 roundings of the largest deviation above 4e-15 (bound 40)", flush=True)
+    # mapping of sampled spheres against the closed-ball rule
+    x = g.spheres()["x"]
+    flags = g.field("flags")
+    owner = g.field("owner")
+    R = wl.R
+    reach = np.sqrt(3.0) * (R.max() + 3.0) + R.max() + 2.0 + 1.0
+    for i in rng.choice(P, 20, replace=False):
+        lo = np.floor(x[i] - R[i] - 3).astype(int)
+        hi = np.floor(x[i] + R[i] + 3).astype(int) + 1
+        lo[2], hi[2] = max(lo[2], 0), min(hi[2], n[2])
+        dd = x - x[i]
+        for a in range(2):
+            dd[:, a] -= n[a] * np.round(dd[:, a] / n[a])
+        near = np.nonzero(np.linalg.norm(dd, axis=1) < reach)[0]
+        (K, J, I), code, own = _expected_codes(lo, hi, x[near], R[near], 2.0, n, (0, 0, 1))
+        own = np.where(own >= 0, near[np.maximum(own, 0)], -1)
+        assert np.array_equal(flags[K, J, I], code), f"flags of sphere {i} box differ"
+        sol = code == 2
+        assert np.array_equal(owner[K, J, I][sol], own[sol]), f"owners of sphere {i} box differ"
+    print("  mapping of 20 sampled sphere boxes bit-exact after 11 steps", flush=True)
+    g.close()
