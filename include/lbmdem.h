@@ -68,7 +68,15 @@ enum {
   LBMDEM_FIELD_PDF = 2,   /* double[19N], full f (not the stored deviation) */
   LBMDEM_FIELD_FLAGS = 3, /* uint8[N]: 0 fluid, 1 fluid in TRT+aB shell,
                              2 solid, 3 wall                                */
-  LBMDEM_FIELD_OWNER = 4  /* int32[N]: sphere id of solid cells, else -1   */
+  LBMDEM_FIELD_OWNER = 4, /* int32[N]: sphere id of solid cells, else -1   */
+  LBMDEM_FIELD_PDF_RAW = 5 /* double[19N]: what every cell's slots hold, solid
+                              cells included (full f: stored value + w_q); the
+                              slot of direction q of a solid cell y holds the
+                              boundary value, Eq. (MEM_CLI), of the particle
+                              link that streams from y into the fluid cell
+                              y + c_q at the next step (written by the separate
+                              boundary pass; map_kernel 3 forms it in the
+                              sweep instead and leaves the slot unused)      */
 };
 
 typedef struct lbmdem_config {

@@ -203,6 +203,7 @@ int32_t lbmdem_ref_get_field(lbmdem_ref_domain* dom, int32_t field, void* dst, s
     case 2: need = 152 * N; break;
     case 3: need = N; break;
     case 4: need = 4 * N; break;
+    case 5: return fail(dom, -1, "the oracle keeps no boundary values in solid cells (field 5)");
     default: return fail(dom, -1, "unknown field");
   }
   if (bytes < need) return fail(dom, -1, "destination too small");

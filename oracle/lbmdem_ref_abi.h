@@ -9,7 +9,9 @@
  *
  * Differences from the GPU calls: device regions and streams are not used
  * (dev_buf must be NULL, hip_stream is ignored); fields are copied to host
- * memory only; lbmdem_ref_update_spheres re-maps after each sphere in turn;
+ * memory only, and the raw PDF field (5: boundary values kept in solid cells)
+ * does not exist here; lbmdem_ref_update_spheres re-maps after each sphere in
+ * turn;
  * lbmdem_ref_sync has nothing to wait for.
  */
 #ifndef LBMDEM_REF_ABI_H

@@ -1085,6 +1085,7 @@ int32_t lbmdem_get_field(lbmdem_domain* dom, int32_t field, void* dst, size_t by
     case LBMDEM_FIELD_PDF: need = 8 * N * Q; first = 10; planes = Q; break;
     case LBMDEM_FIELD_FLAGS: need = N; first = 40; planes = 1; break;
     case LBMDEM_FIELD_OWNER: need = 4 * N; first = 41; planes = 1; break;
+    case LBMDEM_FIELD_PDF_RAW: need = 8 * N * Q; first = 60; planes = Q; break;
     default: return fail(dom, LBMDEM_EINVAL, "unknown field");
   }
   if (bytes < need) return fail(dom, LBMDEM_EINVAL, "destination too small");

@@ -39,7 +39,8 @@ __device__ inline double to_d<__half>(__half v) {
 }
 
 // which: 0 rho, 1..3 velocity component, 10+q PDF plane q (full f),
-// 40 canonical flags, 41 owner (as double)
+// 40 canonical flags, 41 owner (as double), 60+q plane q as stored (full f)
+// in every cell, solid and wall cells included
 template <typename T>
 __global__ void k_get_plane(DevDomain d, int which, double* dst) {
   const int cur = d.ctl->cur;
@@ -54,6 +55,9 @@ __global__ void k_get_plane(DevDomain d, int which, double* dst) {
       v = (fl & F_WALL) ? 3.0 : ((fl & F_SOLID) ? 2.0 : ((fl & F_SHELL) ? 1.0 : 0.0));
     } else if (which == 41) {
       v = (fl & F_SOLID) ? (double)d.owner[c] : -1.0;
+    } else if (which >= 60) {
+      const int q = which - 60;
+      v = to_d<T>(f[(size_t)q * N + c]) + WQ[q];
     } else if (fluid) {
       if (which >= 10) {
         const int q = which - 10;

@@ -26,7 +26,7 @@ BC_CLI, BC_BOUNCE_BACK = 0, 1
 STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
 FREE, PRESCRIBED, FIXED = 0, 1, 2
 STOP_NONE, STOP_REBOUND = 0, 1
-FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_FLAGS, FIELD_OWNER = 0, 1, 2, 3, 4
+FIELD_RHO, FIELD_VEL, FIELD_PDF, FIELD_FLAGS, FIELD_OWNER, FIELD_PDF_RAW = 0, 1, 2, 3, 4, 5
 SPHERE_STATE = 42
 
 
@@ -327,6 +327,9 @@ class Domain:
         elif which == "owner":
             out = np.zeros(self.N, dtype=np.int32)
             shape, fid = (nz, ny, nx), FIELD_OWNER
+        elif which == "pdf_raw":
+            out = np.zeros(19 * self.N)
+            shape, fid = (19, nz, ny, nx), FIELD_PDF_RAW
         else:
             raise ValueError(which)
         self._check(lib().lbmdem_get_field(self.h, fid, C.c_void_p(out.ctypes.data), out.nbytes, 0))
@@ -334,10 +337,10 @@ class Domain:
 
     def field_into(self, which: str, out) -> None:
         """Synchronising copy of a whole-lattice field into the device tensor
-        `out` (float64 rho (N), vel (3N) or pdf (19N); uint8 flags; int32
-        owner), for fields too large to bring to the host."""
+        `out` (float64 rho (N), vel (3N), pdf or pdf_raw (19N); uint8 flags;
+        int32 owner), for fields too large to bring to the host."""
         fid = {"rho": FIELD_RHO, "vel": FIELD_VEL, "pdf": FIELD_PDF, "flags": FIELD_FLAGS,
-               "owner": FIELD_OWNER}[which]
+               "owner": FIELD_OWNER, "pdf_raw": FIELD_PDF_RAW}[which]
         self._check(lib().lbmdem_get_field(self.h, fid, C.c_void_p(out.data_ptr()),
                                            out.numel() * out.element_size(), 1))
 
