@@ -965,7 +965,8 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
           code[u] = ss[u] == stamp ? L_SHELL : L_FLUID;
         }
       }
-      st[t] = code[u];
+      // bits 3-5: the flag byte loaded (at most 7), bit 6: none loaded
+      st[t] = code[u] | (ld[u] ? (uint8_t)(fl[u] << 3) : (uint8_t)0x40);
     }
   }
   __syncthreads();
@@ -989,7 +990,8 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     if (!(cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) && !(cell_d2(d, ijk[0], ijk[1], ijk[2], xo) <= rs2))
       continue;
     const long long c = cidx(d, ijk[0], ijk[1], ijk[2]);
-    const uint8_t sc = in ? st[h[0] + he * (h[1] + he * h[2])] : L_UNSET;
+    const uint8_t sv = in ? st[h[0] + he * (h[1] + he * h[2])] : (uint8_t)(L_UNSET | 0x40);
+    const uint8_t sc = sv & 7, of = sv >> 3;  // of = 8: no flag byte loaded
     if (sc == L_WALL || sc == L_OTHER) continue;
     uint8_t nf;
     int no = -1;
@@ -1004,10 +1006,14 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
       nf = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
       if (ns != S_SOLID) no = -1;
     }
-    // (storing only where the state changes was measured slower)
-    d.flags[c] = nf;
+    // every block that commits a cell stores the same byte, so one that
+    // loaded the new byte already may skip it
+    if (of != nf) d.flags[c] = nf;
     if (no >= 0) d.owner[c] = no;
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < NS; t += blockDim.x) st[t] &= 7;
+  __syncthreads();
 
   // 3. solid cells of this sphere with a neighbour that is not, listed in
   // cube order (ordered compaction: wavefront ballots and per-wave offsets),
