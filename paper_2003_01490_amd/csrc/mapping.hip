@@ -918,8 +918,8 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     long long cc[8];
     uint8_t code[8], fl[8];
     unsigned long long kc[8];
-    uint32_t ss[8];
     bool ld[8];
+    uint32_t shell = 0u;  // bit u: within R + delta_aB of the centre
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * blockDim.x;
@@ -939,9 +939,13 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
         }
         if (out) {
           code[u] = L_WALL;
-        } else if (cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rl2) {
-          cc[u] = cidx(d, ijk[0], ijk[1], ijk[2]);
-          ld[u] = true;
+        } else {
+          const double d2 = cell_d2(d, ijk[0], ijk[1], ijk[2], xp);
+          if (d2 <= rl2) {
+            cc[u] = cidx(d, ijk[0], ijk[1], ijk[2]);
+            ld[u] = true;
+            if (d2 <= rs2) shell |= 1u << u;
+          }
         }
       }
     }
@@ -950,7 +954,6 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
       if (ld[u]) {
         fl[u] = d.flags[cc[u]];
         kc[u] = d.claim[cc[u]];
-        ss[u] = d.shellstamp[cc[u]];
       }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -962,7 +965,10 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
         } else if ((uint32_t)(kc[u] >> 32) == stamp) {
           code[u] = (int)(0xFFFFFFFFu - (uint32_t)(kc[u] & 0xFFFFFFFFull)) == i ? L_OWN : L_OTHER;
         } else {
-          code[u] = ss[u] == stamp ? L_SHELL : L_FLUID;
+          // fluid: in this sphere's shell by the claims' own test on the same
+          // position; farther out the shells of other spheres are not known
+          // here (L_FLUID), and step 2 reads the shell stamp where it needs it
+          code[u] = (shell >> u) & 1u ? L_SHELL : L_FLUID;
         }
       }
       // bits 3-5: the flag byte loaded (at most 7), bit 6: none loaded
@@ -998,8 +1004,10 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     if (sc == L_OWN) {
       nf = F_SOLID;
       no = i;
-    } else if (sc == L_SHELL || sc == L_FLUID) {
-      nf = sc == L_SHELL ? F_SHELL : (uint8_t)0;
+    } else if (sc == L_SHELL) {
+      nf = F_SHELL;
+    } else if (sc == L_FLUID) {  // only in the shell of the old position
+      nf = d.shellstamp[c] == stamp ? F_SHELL : (uint8_t)0;
     } else {
       const int ns = new_state(d, c, stamp, &no);
       if (ns == S_WALL) continue;
