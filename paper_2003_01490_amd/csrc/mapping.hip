@@ -441,8 +441,12 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
   // A cell leaves sphere i only if its centre was inside the old ball and is
   // outside the new one: the same FP64 test both mappings made, so only this
   // thin shell of cells touches memory.  Cells to rebuild are listed in LDS
-  // and then rebuilt one wavefront each.
-  FOR_BOX_CELLS(d, bx, b, d.ZB, {
+  // and then rebuilt one wavefront each.  One thread per x-row of the box
+  // applies that test only where it can hold: on the cells within 1e-3 of the
+  // old ball's chord of the row that do not lie more than 1e-3 inside the new
+  // ball's chord (rounding moves a chord's end by far less), i.e. near its two
+  // ends; a box that spans a whole periodic x axis is scanned cell by cell.
+  auto visit = [&](int ii, int jj, int kk) {
     if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
       const long long c = cidx(d, ii, jj, kk);
       if ((d.flags[c] & F_SOLID) && d.owner[c] == i) {
@@ -456,7 +460,47 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
         }
       }
     }
-  })
+  };
+  constexpr double EPS = 1e-3;
+  const int nsl = b < bx.ext[2] ? (bx.ext[2] - 1 - b) / d.ZB + 1 : 0;
+  const int nrows = bx.ext[1] * nsl;
+  const bool whole_x = !d.walls[0] && bx.ext[0] >= d.nx;
+  // the new centre's x next to the old one (the box's coordinates are not
+  // wrapped: the old centre's offsets in them are the minimum images)
+  const double xn0 = xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0]);
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    const int ty = r % bx.ext[1], sl = b + d.ZB * (r / bx.ext[1]);
+    const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
+    const int kk = d.walls[2] ? bx.lo[2] + sl : wrap_near(bx.lo[2] + sl, d.nz);
+    const int g0 = bx.lo[0], g1 = bx.lo[0] + bx.ext[0] - 1;
+    // the cells to test: [s0, e0] and [s1, e1]
+    int s0 = g0, e0 = g1, s1 = 1, e1 = 0;
+    if (!whole_x) {
+      const double oy = min_image(((double)jj + 0.5) - xo[1], d.ny, d.walls[1]);
+      const double oz = min_image(((double)kk + 0.5) - xo[2], d.nz, d.walls[2]);
+      const double ro = R2 - (oy * oy + oz * oz);
+      const double ao = sqrt(fmax(ro, 0.0)) + EPS;
+      const double ny_ = min_image(((double)jj + 0.5) - xn[1], d.ny, d.walls[1]);
+      const double nz_ = min_image(((double)kk + 0.5) - xn[2], d.nz, d.walls[2]);
+      const double rn = R2 - (ny_ * ny_ + nz_ * nz_);
+      const double an = rn > 0.0 ? sqrt(rn) - EPS : -1.0;  // cells closer are inside
+      // cell g's centre is g + 0.5: the old chord covers [s0, e0] (none when
+      // the row misses the old ball); the sure inside of the new one, cells
+      // with |g + 0.5 - xn0| < an, is [C, D] (none when an <= 0)
+      s0 = max(g0, (int)ceil(xo[0] - ao - 0.5));
+      e0 = ro < -EPS ? s0 - 1 : min(g1, (int)floor(xo[0] + ao - 0.5));
+      if (an > 0.0) {
+        const int C = (int)floor(xn0 - an - 0.5) + 1, D = (int)ceil(xn0 + an - 0.5) - 1;
+        s1 = max(s0, D + 1);
+        e1 = e0;
+        e0 = min(e0, C - 1);
+      }
+    }
+    for (int seg = 0; seg < 2; ++seg) {
+      const int gs = seg ? s1 : s0, ge = seg ? e1 : e0;
+      for (int g = gs; g <= ge; ++g) visit(d.walls[0] ? g : wrap_near(g, d.nx), jj, kk);
+    }
+  }
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
