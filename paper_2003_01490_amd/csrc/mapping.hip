@@ -957,7 +957,34 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   int lo[3];
   for (int a = 0; a < 3; ++a) lo[a] = finite ? (int)floor(xp[a]) - H : 0;
 
-  // 1. stage: eight cells per thread and pass, all loads issued before use
+  // Row chords, kept in the link list's LDS (unused until step 4): of each
+  // x-row of a box, the cells whose centres can lie within a radius of a
+  // centre are those with x index in [s, e] (packed s | e << 16; s > e: none),
+  // from the row's exact y and z offsets, widened by 1e-3, far more than
+  // rounding moves a chord's end; the exact tests then run on those cells
+  // only.  Rows of a box that nearly spans a periodic x axis keep every cell.
+  constexpr double EPS = 1e-3;
+  constexpr int CH = (Q - 1) * BALL_THREADS;
+  uint32_t* chord = lk;
+  const bool chorded1 = he * he <= CH && (d.walls[0] || he + 2 <= n[0]);
+  if (chorded1) {
+    for (int r = threadIdx.x; r < he * he; r += blockDim.x) {
+      const int gy = lo[1] + r % he, gz = lo[2] + r / he;
+      const int jj = d.walls[1] ? gy : wrap_near(gy, n[1]), kk = d.walls[2] ? gz : wrap_near(gz, n[2]);
+      const double dy = min_image(((double)jj + 0.5) - xp[1], n[1], d.walls[1]);
+      const double dz = min_image(((double)kk + 0.5) - xp[2], n[2], d.walls[2]);
+      const double rho = rl2 - (dy * dy + dz * dz);
+      const double a = sqrt(fmax(rho, 0.0)) + EPS;
+      int s0 = max(0, (int)ceil(xp[0] - a - 0.5) - lo[0]), e0 = min(he - 1, (int)floor(xp[0] + a - 0.5) - lo[0]);
+      if (rho < -EPS || e0 < s0) s0 = 1, e0 = 0;
+      chord[r] = (uint32_t)s0 | ((uint32_t)e0 << 16);
+    }
+    __syncthreads();
+  }
+
+  // 1. stage: eight cells per thread and pass, all loads issued before use;
+  // the cells within R + 3 of the centre (those of the row chords) are
+  // loaded: every link's y - c_q and y - 2 c_q lies within R + 2 sqrt(2)
   for (int t0 = threadIdx.x; t0 < NS; t0 += 8 * blockDim.x) {
     long long cc[8];
     uint8_t code[8], fl[8];
@@ -984,11 +1011,12 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
         if (out) {
           code[u] = L_WALL;
         } else {
-          const double d2 = cell_d2(d, ijk[0], ijk[1], ijk[2], xp);
-          if (d2 <= rl2) {
+          const int hx = t % he;
+          const uint32_t ch = chorded1 ? chord[t / he] : 0xFFFF0000u;
+          if (hx >= (int)(ch & 0xFFFFu) && hx <= (int)(ch >> 16)) {
             cc[u] = cidx(d, ijk[0], ijk[1], ijk[2]);
             ld[u] = true;
-            if (d2 <= rs2) shell |= 1u << u;
+            if (cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) shell |= 1u << u;
           }
         }
       }
@@ -1026,8 +1054,38 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   Box bx;
   sphere_box(d, i, true, bx);
   const int nbox = bx.ext[0] * bx.ext[1] * bx.ext[2];
+  // row chords of the union of the two shell balls (the box's x frame is
+  // unwrapped around the new centre)
+  const bool chorded2 = bx.ext[1] * bx.ext[2] <= CH && (d.walls[0] || bx.ext[0] + 2 <= n[0]);
+  if (chorded2) {
+    const double cx[2] = {xp[0], xp[0] + min_image(xo[0] - xp[0], n[0], d.walls[0])};
+    for (int r = threadIdx.x; r < bx.ext[1] * bx.ext[2]; r += blockDim.x) {
+      const int gy = bx.lo[1] + r % bx.ext[1], gz = bx.lo[2] + r / bx.ext[1];
+      const int jj = d.walls[1] ? gy : wrap_near(gy, n[1]), kk = d.walls[2] ? gz : wrap_near(gz, n[2]);
+      int s0 = bx.ext[0], e0 = -1;
+      for (int k = 0; k < 2; ++k) {
+        const double* cc = k ? xo : xp;
+        const double dy = min_image(((double)jj + 0.5) - cc[1], n[1], d.walls[1]);
+        const double dz = min_image(((double)kk + 0.5) - cc[2], n[2], d.walls[2]);
+        const double rho = rs2 - (dy * dy + dz * dz);
+        if (rho < -EPS) continue;
+        const double a = sqrt(fmax(rho, 0.0)) + EPS;
+        s0 = min(s0, (int)ceil(cx[k] - a - 0.5) - bx.lo[0]);
+        e0 = max(e0, (int)floor(cx[k] + a - 0.5) - bx.lo[0]);
+      }
+      s0 = max(s0, 0);
+      e0 = min(e0, bx.ext[0] - 1);
+      if (e0 < s0) s0 = 1, e0 = 0;
+      chord[r] = (uint32_t)s0 | ((uint32_t)e0 << 16);
+    }
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < nbox; t += blockDim.x) {
     const int tx = t % bx.ext[0], ty = (t / bx.ext[0]) % bx.ext[1], tz = t / (bx.ext[0] * bx.ext[1]);
+    if (chorded2) {
+      const uint32_t ch = chord[ty + bx.ext[1] * tz];
+      if (tx < (int)(ch & 0xFFFFu) || tx > (int)(ch >> 16)) continue;
+    }
     const int g[3] = {bx.lo[0] + tx, bx.lo[1] + ty, bx.lo[2] + tz};
     int ijk[3], h[3];
     bool in = true;
