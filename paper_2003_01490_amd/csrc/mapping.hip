@@ -178,6 +178,8 @@ __device__ __forceinline__ bool claims_exclusive(const DevDomain& d, int i) {
   return true;
 }
 
+constexpr int CLAIM_ROWS = 1024;  // row chords a claim block keeps in LDS
+
 __device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_t stamp, bool lists) {
   const int i = blk / d.ZB, b = blk % d.ZB;
   if (i >= d.P) return;
@@ -195,23 +197,58 @@ __device__ __forceinline__ void claim_block(const DevDomain& d, int blk, uint32_
   }
   const unsigned long long key =
       ((unsigned long long)stamp << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+  // x-chords of the box's rows: the cells whose centres can lie within
+  // R + delta_aB of the centre have x index in [s, e] (packed s | e << 16;
+  // s > e: none), from the row's exact y and z offsets widened by 1e-3, far
+  // more than rounding moves a chord's end; the exact tests run on those
+  // cells only.  A box that nearly spans a periodic x axis keeps every cell.
+  __shared__ uint32_t chord[CLAIM_ROWS];
+  const int n[3] = {d.nx, d.ny, d.nz};
+  const bool chorded = bx.ext[1] * bx.ext[2] <= CLAIM_ROWS && (d.walls[0] || bx.ext[0] + 2 <= n[0]);
+  if (chorded) {
+    constexpr double EPS = 1e-3;
+    for (int r = threadIdx.x; r < bx.ext[1] * bx.ext[2]; r += blockDim.x) {
+      const int gy = bx.lo[1] + r % bx.ext[1], gz = bx.lo[2] + r / bx.ext[1];
+      const int jj = d.walls[1] ? gy : wrap_near(gy, n[1]), kk = d.walls[2] ? gz : wrap_near(gz, n[2]);
+      const double dy = min_image(((double)jj + 0.5) - xp[1], n[1], d.walls[1]);
+      const double dz = min_image(((double)kk + 0.5) - xp[2], n[2], d.walls[2]);
+      const double rho = rs2 - (dy * dy + dz * dz);
+      const double a = sqrt(fmax(rho, 0.0)) + EPS;
+      int s0 = max(0, (int)ceil(xp[0] - a - 0.5) - bx.lo[0]);
+      int e0 = min(bx.ext[0] - 1, (int)floor(xp[0] + a - 0.5) - bx.lo[0]);
+      if (rho < -EPS || e0 < s0) s0 = 1, e0 = 0;
+      chord[r] = (uint32_t)s0 | ((uint32_t)e0 << 16);
+    }
+    __syncthreads();
+  }
   // wall layers (the first and last layer of a walled axis) are never
   // claimed; they are known from the coordinates, so no flag is read
-  FOR_BOX_CELLS(d, bx, b, d.ZB, {
-    const long long c = cidx(d, ii, jj, kk);
-    const bool wall = (d.walls[0] && (ii == 0 || ii == d.nx - 1)) || (d.walls[1] && (jj == 0 || jj == d.ny - 1)) ||
-                      (d.walls[2] && (kk == 0 || kk == d.nz - 1));
-    if (!wall) {
-      const double d2 = cell_d2(d, ii, jj, kk, xp);
-      if (d2 <= R2) {
-        if (excl)
-          d.claim[c] = key;
-        else
-          atomicMax(&d.claim[c], key);
+  const int nxy = bx.ext[0] * bx.ext[1];
+  for (int sl = b; sl < bx.ext[2]; sl += d.ZB) {
+    const int kk = d.walls[2] ? bx.lo[2] + sl : wrap_near(bx.lo[2] + sl, d.nz);
+    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
+      const int tx = t % bx.ext[0], ty = t / bx.ext[0];
+      if (chorded) {
+        const uint32_t ch = chord[ty + bx.ext[1] * sl];
+        if (tx < (int)(ch & 0xFFFFu) || tx > (int)(ch >> 16)) continue;
       }
-      if (d2 <= rs2) d.shellstamp[c] = stamp;
+      const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
+      const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
+      const long long c = cidx(d, ii, jj, kk);
+      const bool wall = (d.walls[0] && (ii == 0 || ii == d.nx - 1)) || (d.walls[1] && (jj == 0 || jj == d.ny - 1)) ||
+                        (d.walls[2] && (kk == 0 || kk == d.nz - 1));
+      if (!wall) {
+        const double d2 = cell_d2(d, ii, jj, kk, xp);
+        if (d2 <= R2) {
+          if (excl)
+            d.claim[c] = key;
+          else
+            atomicMax(&d.claim[c], key);
+        }
+        if (d2 <= rs2) d.shellstamp[c] = stamp;
+      }
     }
-  })
+  }
 }
 
 // Whether a mapping kernel runs, which buffer it works on and its stamp:
