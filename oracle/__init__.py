@@ -112,6 +112,9 @@ def lib():
         L.ref_rates.argtypes = [C.POINTER(RefConfig), dp, dp, dp]
         L.ref_equilibrium.argtypes = [C.c_double, dp, dp]
         L.ref_collide.argtypes = [C.POINTER(RefConfig), dp, C.c_int32, dp, dp]
+        L.ref_link_value.restype = C.c_double
+        L.ref_link_value.argtypes = [C.c_int32, dp, C.c_double, dp, dp, C.c_double, C.c_double, C.c_double,
+                                     C.c_int32]
         L.ref_lubrication.argtypes = [C.POINTER(RefConfig), dp, dp, dp, C.c_double, dp, dp,
                                       dp, C.c_double, C.c_int32, dp, dp]
         L.ref_collision_time.restype = C.c_double
@@ -189,6 +192,14 @@ def equilibrium(rho, u):
     out = np.zeros(19)
     lib().ref_equilibrium(float(rho), _dp(_vec(u)), _dp(out))
     return out
+
+
+def link_value(q, r, R, u, w, Aq, Aqb, Aqm, cli):
+    """Eq. (MEM_CLI): the boundary value of one particle link, from the
+    oracle's own link arithmetic (r = x - x_p of the fluid cell, the sphere's
+    R, u, w; Aq = f~_q(x), Aqb = f~_qbar(x), Aqm = f~_q(x - c_q) with CLI)."""
+    return lib().ref_link_value(int(q), _dp(_vec(r)), float(R), _dp(_vec(u)), _dp(_vec(w)), float(Aq), float(Aqb),
+                                float(Aqm), int(bool(cli)))
 
 
 def collide(cfg: RefConfig, f, shell=False, force=None):

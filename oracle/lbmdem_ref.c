@@ -543,6 +543,34 @@ static double link_delta(const double* r, const int* c, double R) {
   return dl;
 }
 
+/* Eq. (MEM_CLI) for one particle link: the value that streams back into the
+ * fluid cell x from the solid cell x + c_q, from f~_q(x) (Aq), f~_qbar(x)
+ * (Aqb) and, with CLI (cli != 0), f~_q(x - c_q) (Aqm); r = x - x_p (nearest
+ * image) and R, u, w of the sphere.  rb and ub receive the wall point's offset
+ * r + delta c_q and its velocity, for the force of Eq. (MEM_Fq). */
+static double link_value(int q, const double* r, double R, const double* u, const double* w, double Aq,
+                         double Aqb, double Aqm, int cli, double* rb, double* ub) {
+  double cq[3] = {LC[q][0], LC[q][1], LC[q][2]};
+  double dl = link_delta(r, LC[q], R);
+  for (int a = 0; a < 3; ++a) rb[a] = r[a] + dl * cq[a];
+  double wr[3];
+  cross(w, rb, wr);
+  for (int a = 0; a < 3; ++a) ub[a] = u[a] + wr[a];
+  double dd = cli ? dl : 0.5;
+  double val = Aq;
+  if (cli)
+    val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (Aqm - Aqb);
+  val -= 4.0 / (1.0 + 2.0 * dd) * LW[q] * 3.0 * dot3(ub, cq);
+  return val;
+}
+
+double ref_link_value(int32_t q, const double* r, double R, const double* u, const double* w, double Aq,
+                      double Aqb, double Aqm, int32_t cli) {
+  double rb[3], ub[3];
+  if (q < 1 || q >= NQ) return NAN;
+  return link_value(q, r, R, u, w, Aq, Aqb, Aqm, cli, rb, ub);
+}
+
 static void boundary_and_forces(ref_domain* d, double* F) {
   const long N = d->N;
   const double* A = d->A;
@@ -571,20 +599,14 @@ static void boundary_and_forces(ref_domain* d, double* F) {
             r[0] = minimg(d, 0, ((double)i + 0.5) - s->x[0]);
             r[1] = minimg(d, 1, ((double)j + 0.5) - s->x[1]);
             r[2] = minimg(d, 2, ((double)k + 0.5) - s->x[2]);
-            double dl = link_delta(r, LC[q], s->R);
-            double rb[3], ub[3];
-            for (int a = 0; a < 3; ++a) rb[a] = r[a] + dl * cq[a];
-            body_velocity(s, rb, ub);
             int mi = wrapi(i - LC[q][0], d->n[0]);
             int mj = wrapi(j - LC[q][1], d->n[1]);
             int mk = wrapi(k - LC[q][2], d->n[2]);
             long xm = cidx(d, mi, mj, mk);
             int cli = d->cfg.boundary == 0 && is_fluid_code(d->code[xm]);
-            double dd = cli ? dl : 0.5;
-            double val = A[q * N + x];
-            if (cli)
-              val += (1.0 - 2.0 * dd) / (1.0 + 2.0 * dd) * (A[q * N + xm] - A[qb * N + x]);
-            val -= 4.0 / (1.0 + 2.0 * dd) * LW[q] * 3.0 * dot3(ub, cq);
+            double rb[3], ub[3];
+            double val = link_value(q, r, s->R, s->u, s->w, A[q * N + x], A[qb * N + x], cli ? A[q * N + xm] : 0.0,
+                                    cli, rb, ub);
             d->fb[qb * N + x] = val;
             /* Eq. (MEM_Fq) */
             double Fq[3], Tq[3];

@@ -33,7 +33,7 @@ def gpu_domain(wl: W.Workload, storage=0, device="cuda:0", stream=None, **over):
     gkeys = {f[0] for f in L.Config._fields_}
     p = {k: v for k, v in p.items() if k in gkeys}
     p["storage"] = storage
-    p["max_radius"] = float(max(wl.R)) if len(wl.R) else 1.0
+    p["max_radius"] = over.get("max_radius", float(max(wl.R)) if len(wl.R) else 1.0)
     p["max_spheres"] = max(p.get("max_spheres", 1), len(wl.R), 1)
     d = L.Domain(L.default_config(**p), device=device, stream=stream)
     if len(wl.R):

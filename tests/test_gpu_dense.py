@@ -73,10 +73,14 @@ def _compare_fields(g, o, tol=TOL):
 def test_dense_agitated_fp64_both_kernels():
     wl = W.dense(3, n=48, count=40, D=8.0, min_gap=0.2, u_rms=0.05, nu=0.01)
     P = len(wl.R)
-    _case(f"agitated 48^3, {P} spheres, FP64, (DEM, map) kernels (1,1) (2,1) (2,2) (2,3)")
+    _case(f"agitated 48^3, {P} spheres, FP64, (DEM, map) kernels (1,1) (2,1) (2,2) (2,3), "
+          "(2,2) with max_radius 10")
     o = oracle_domain(wl)
+    # the last domain's boundary pass stages a larger cube (edge 29 for
+    # max_radius 10 against 17): the same bits as the (2,2) domain
     gs = [gpu_domain(wl, dem_kernel=1, map_kernel=1), gpu_domain(wl, dem_kernel=2, map_kernel=1),
-          gpu_domain(wl, dem_kernel=2, map_kernel=2), gpu_domain(wl, dem_kernel=2, map_kernel=3)]
+          gpu_domain(wl, dem_kernel=2, map_kernel=2), gpu_domain(wl, dem_kernel=2, map_kernel=3),
+          gpu_domain(wl, dem_kernel=2, map_kernel=2, max_radius=10.0)]
     u_scale = float(np.abs(wl.u).max())
     F_scale = 0.0
     contacts = lub = 0
@@ -94,6 +98,7 @@ def test_dense_agitated_fp64_both_kernels():
                                    for s in so))
         _check_spheres(gs, so, 8.0, {"u": u_scale, "F": F_scale}, f"step {chk}", fp64_bounds(F_raw=2e-12))
         assert _same_state(gs[0], gs[1]), "DEM kernels differ"
+        assert _same_state(gs[2], gs[4]), "boundary pass differs with the staged cube's edge"
     print(f"  sphere-checkpoints in contact {contacts}, in lubrication range {lub}", flush=True)
     assert contacts > 0 and lub > 0
     for g in gs:
@@ -259,7 +264,11 @@ def test_headline_512_sampled_against_oracle():
       rounding per deviation summed into the moments and per relaxed term,
       and the rounding of the stored result; 11.9 observed) plus 4e-15 for
       the oracle's FP64 rounding on full f; shell cells (TRT+aB) included;
-    * the mapping of 20 sampled sphere boxes against the closed-ball rule."""
+    * the mapping of 20 sampled sphere boxes against the closed-ball rule;
+    * the boundary values of ~1,000 sampled particle links, Eq. (MEM_CLI),
+      stored in the solid cells' slots, against the oracle's link arithmetic
+      fed with the GPU's own post-collision values and sphere state, within
+      one FP32 rounding of their deviation from w_q."""
     import torch
     from paper_2003_01490_amd import lbmdem as L
 
@@ -338,4 +347,57 @@ def test_headline_512_sampled_against_oracle():
         sol = code == 2
         assert np.array_equal(owner[K, J, I][sol], own[sol]), f"owners of sphere {i} box differ"
     print("  mapping of 20 sampled sphere boxes bit-exact after 11 steps", flush=True)
+    # boundary values of sampled particle links (Eq. MEM_CLI), written by the
+    # boundary pass into the solid cells' slots, against the oracle's link
+    # arithmetic fed with the GPU's own post-collision values and sphere state
+    # (the pass computes in FP64 from the stored values; the result is stored
+    # in FP32: one rounding of the value's deviation from w_q)
+    st = g.spheres()
+    links = []
+    for i in rng.choice(P, 20, replace=False):
+        lo = np.floor(st["x"][i] - R[i] - 2).astype(int)
+        hi = np.floor(st["x"][i] + R[i] + 2).astype(int) + 1
+        gz, gy, gx = np.meshgrid(np.arange(max(lo[2], 0), min(hi[2], n[2])), np.arange(lo[1], hi[1]),
+                                 np.arange(lo[0], hi[0]), indexing="ij")
+        X = np.stack([gx.ravel() % n[0], gy.ravel() % n[1], gz.ravel()], axis=1)
+        X = X[flags[X[:, 2], X[:, 1], X[:, 0]] <= 1]
+        for q in range(1, 19):
+            Y = X + c[q]
+            Y[:, 0] %= n[0]
+            Y[:, 1] %= n[1]
+            inside = (Y[:, 2] >= 0) & (Y[:, 2] < n[2])
+            sel = np.nonzero(inside)[0]
+            hit = sel[(flags[Y[sel, 2], Y[sel, 1], Y[sel, 0]] == 2) & (owner[Y[sel, 2], Y[sel, 1], Y[sel, 0]] == i)]
+            for h in rng.choice(hit, min(3, len(hit)), replace=False):
+                links.append((int(i), q, X[h], Y[h]))
+    assert len(links) >= 500
+    # int64 throughout: plane offsets q N reach 18 * 512^3 > 2^31
+    opp = O.lattice()[2].astype(np.int64)
+    qs = np.array([l[1] for l in links], dtype=np.int64)
+    Xs = np.array([l[2] for l in links])
+    Ys = np.array([l[3] for l in links])
+    Ms = Xs - c[qs]
+    Ms[:, 0] %= n[0]
+    Ms[:, 1] %= n[1]
+    flat = lambda A: A[:, 0] + n[0] * (A[:, 1] + n[1] * A[:, 2])
+    want = np.stack([qs * N + flat(Xs), opp[qs] * N + flat(Xs), qs * N + flat(Ms), opp[qs] * N + flat(Ys)], axis=1)
+    assert want.dtype == np.int64 and want.min() >= 0 and want.max() < 19 * N
+    raw = torch.empty(19 * N, dtype=torch.float64, device=dev)
+    g.field_into("pdf_raw", raw)
+    vals = raw[torch.from_numpy(want).to(dev)].cpu().numpy()
+    del raw
+    torch.cuda.empty_cache()
+    cli_on = flags[Ms[:, 2], Ms[:, 1], Ms[:, 0]] <= 1
+    worst = 0.0
+    for k, (i, q, xcell, _) in enumerate(links):
+        r = (xcell + 0.5) - st["x"][i]
+        for a in range(2):
+            r[a] -= n[a] * np.round(r[a] / n[a])
+        ref = O.link_value(q, r, R[i], st["u"][i], st["w"][i], vals[k, 0], vals[k, 1], vals[k, 2], cli_on[k])
+        dv = abs(ref - w[opp[q]])
+        e = abs(vals[k, 3] - ref)
+        worst = max(worst, (e - 1e-15) / max(dv * 2.0 ** -24, 1e-300))
+        assert e <= dv * 2.0 ** -24 + 1e-15, (i, q, xcell, vals[k], ref)
+    print(f"  {len(links)} sampled particle links ({int(cli_on.sum())} with CLI): boundary values within "
+          f"{max(worst, 0.0):.2f} FP32 roundings of their deviation (bound 1)", flush=True)
     g.close()

@@ -352,3 +352,38 @@ def test_settling_sphere_on_symmetry_point_keeps_symmetry():
     assert np.abs(s["T_raw"]).max() < 1e-12
     assert abs(s["x"][0] - 8.0) < 1e-12 and abs(s["x"][1] - 8.0) < 1e-12
     assert s["u"][2] < 0
+
+
+def test_link_value_coefficients_of_cli():
+    """Eq. (MEM_CLI) for single links placed by hand: a fluid cell whose link
+    along c_q = (1, 0, 0) meets the sphere surface a quarter cell away
+    (delta = 1/4, CLI coefficients (1 - 2 delta)/(1 + 2 delta) = 1/3 and
+    4/(1 + 2 delta) = 8/3); the same geometry without a second fluid node
+    (bounce-back, delta read as 1/2: plain bounce-back plus 6 w_q u.c_q, the
+    moving-wall rule); and a rotating sphere, whose wall-point velocity is
+    u + w x r_b at r_b = r + delta c_q."""
+    c, w, opp = O.lattice()
+    q = int(np.nonzero((c == [1, 0, 0]).all(axis=1))[0][0])
+    R = 3.0
+    r = np.array([-(R + 0.25), 0.0, 0.0])  # |r + delta c| = R at delta = 1/4
+    Aq, Aqb, Aqm = 0.061, 0.049, 0.058
+    assert abs(O.link_value(q, r, R, [0, 0, 0], [0, 0, 0], Aq, Aqb, Aqm, True) - (Aq + (Aqm - Aqb) / 3)) < 1e-16
+    u = np.array([0.01, -0.02, 0.03])
+    got = O.link_value(q, r, R, u, [0, 0, 0], Aq, Aqb, Aqm, True)
+    assert abs(got - (Aq + (Aqm - Aqb) / 3 - 8.0 / 3.0 * w[q] * 3.0 * u[0])) < 1e-16
+    got = O.link_value(q, r, R, u, [0, 0, 0], Aq, Aqb, Aqm, False)
+    assert abs(got - (Aq - 6.0 * w[q] * u[0])) < 1e-16
+    # rotation about z: the wall point r_b = (-R, 0, 0) moves with w x r_b = (0, -R wz, 0),
+    # which has no component along c_q; rotation about y gives (0, 0, R wy) x ... likewise 0;
+    # a diagonal link sees it: c = (1, 1, 0)
+    q2 = int(np.nonzero((c == [1, 1, 0]).all(axis=1))[0][0])
+    r2 = np.array([-(R + 0.25), 0.0, 0.0])
+    wz = 0.004
+    # delta from |r2 + d c|^2 = R^2: (-(R + 1/4) + d)^2 + d^2 = R^2
+    a, b, cc = 2.0, -2.0 * (R + 0.25), (R + 0.25) ** 2 - R * R
+    d = (-b - np.sqrt(b * b - 4 * a * cc)) / (2 * a)
+    rb = r2 + d * np.array([1.0, 1.0, 0.0])
+    ub = np.cross([0.0, 0.0, wz], rb)
+    expect = Aq + (1 - 2 * d) / (1 + 2 * d) * (Aqm - Aqb) - 4.0 / (1 + 2 * d) * w[q2] * 3.0 * (ub[0] + ub[1])
+    got = O.link_value(q2, r2, R, [0, 0, 0], [0, 0, wz], Aq, Aqb, Aqm, True)
+    assert abs(got - expect) < 1e-15, (got, expect)
