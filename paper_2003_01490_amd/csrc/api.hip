@@ -180,16 +180,17 @@ Layout make_layout(const lbmdem_config& c) {
   L.shellstamp = take(4 * N);
   L.cellw = take(use_fused(c) ? 4 * N : 0);  // fused step: flags | (owner + 1) << 8
   L.stage = take(8 * N);
-  // fused step only (transient, so not part of a checkpoint)
+  // fused step (tile slots) and geometric mapping (bins of the fused step and
+  // the ball pass) only; transient, so not part of a checkpoint
   {
-    const bool f = use_fused(c);
+    const bool f = use_fused(c), geo = f || use_ball(c);
     const FusedGeom g = fused_geom(c);
     const size_t per = f ? (size_t)g.snx * g.sny * g.snz : 0;
     int mb[3] = {1, 1, 1};
-    if (f) mbin_dims(c, mb);
+    if (geo) mbin_dims(c, mb);
     L.slot = take(48 * P * per);
     L.slot_stamp = take(4 * P * per);
-    L.mbins = take(f ? 4 * (size_t)mb[0] * mb[1] * mb[2] * (1 + BIN_CAP) : 0);
+    L.mbins = take(geo ? 4 * (size_t)mb[0] * mb[1] * mb[2] * (1 + BIN_CAP) : 0);
   }
   L.x = take(24 * P);
   L.u = take(24 * P);
@@ -401,7 +402,7 @@ static int32_t refresh_order(lbmdem_domain* dom) {
 static int32_t remap(lbmdem_domain* dom, bool reconstruct) {
   dom->d.P = (int)dom->hR.size();
   if (dom->d.fused) {
-    timed(dom, 2, dom->stream, [&] { launch_mapping_fused(dom->d, reconstruct, dom->stream); });
+    timed(dom, 2, dom->stream, [&] { launch_mapping_geo(dom->d, reconstruct, dom->stream); });
     HIPCHK(dom, hipGetLastError());
     return LBMDEM_OK;
   }
@@ -600,7 +601,7 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
     d.sl_per = d.fused ? g.snx * g.sny * g.snz : 0;
     d.slot = (double*)(base + L.slot);
     d.slot_stamp = (uint32_t*)(base + L.slot_stamp);
-    if (d.fused) mbin_dims(*cfg, d.mbins.n);
+    if (d.fused || d.map_ball) mbin_dims(*cfg, d.mbins.n);
     else d.mbins.n[0] = d.mbins.n[1] = d.mbins.n[2] = 1;
     d.mbins.cell = (int*)(base + L.mbins);
     d.stage32 = (uint32_t*)(base + L.stage);
@@ -891,7 +892,7 @@ static int32_t step_direct(lbmdem_domain* dom, int32_t nsteps) {
     auto dem = [&] {
       timed(dom, 1, ds, [&] {
         e = launch_dem(dom->d, dom->cfg.dem_kernel, !dom->may_prescribe, ds);
-        launch_claim(dom->d, 1, dem_many(dom->d, dom->cfg.dem_kernel), ds);
+        launch_map_prepare(dom->d, dem_many(dom->d, dom->cfg.dem_kernel), ds);
       });
     };
     if (!ov) {

@@ -327,18 +327,20 @@ __device__ inline void step_control(const DevDomain& d) {
 
 // host-side launchers (implemented in the .hip files)
 void launch_sweep(const DevDomain& d, hipStream_t s);
-// mapping update outside the step: claim + (reconstruction) + commit/boundary
-// values on the current buffer, then the new stamp, in order on one stream
+// mapping update outside the step: the flags and owners of the current
+// positions (claims, or the geometric update of the ball pass), the
+// (reconstruction), the boundary values on the current buffer, then the new
+// stamp, in order on one stream
 void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s);
-// the claim kernel alone (needs only the particle positions), and the rest;
-// in_step = 1 inside a step (after the sweep and the DEM, before the step
-// control), 0 for an update outside the step
-// lists: the step's many-sphere neighbour lists are valid (claims of spheres
-// that meet no other sphere then need no atomics)
-void launch_claim(const DevDomain& d, int in_step, bool lists, hipStream_t s);
-void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s);
-// the same inside a step, ending with the step control (folded into the last
-// block of the boundary pass, or its own kernel when there is none)
+// inside a step, the part of the mapping update that needs only the new
+// positions (after the DEM, beside or after the sweep): the claims of the slab
+// pass (lists: the step's many-sphere neighbour lists are valid, so spheres
+// that meet no other claim without atomics), or the mapping bins of the ball
+// pass
+void launch_map_prepare(const DevDomain& d, bool lists, hipStream_t s);
+// the rest inside a step (after the sweep): reconstruction, flags and owners,
+// boundary values, ending with the step control (folded into the last block
+// of the boundary pass, or its own kernel when there is none)
 void launch_update_and_advance(const DevDomain& d, hipStream_t s);
 // step control (last kernel of a step): freeze, or count the step, flip the
 // buffers, move the stamp and evaluate the stop rule
@@ -373,7 +375,8 @@ void launch_force_reduce(const DevDomain& d, hipStream_t s);
 // fused step after the DEM: mapping bins of the new positions, reconstruction,
 // flags and owners of the cells that change, step control
 void launch_update_fused(const DevDomain& d, hipStream_t s);
-// mapping of the current positions outside a step (every cell evaluated)
-void launch_mapping_fused(const DevDomain& d, bool reconstruct, hipStream_t s);
+// flags, owners and (reconstruction) of the current positions outside a
+// step, every cell evaluated from the mapping bins (fused step, ball pass)
+void launch_mapping_geo(const DevDomain& d, bool reconstruct, hipStream_t s);
 
 }  // namespace lbmdem

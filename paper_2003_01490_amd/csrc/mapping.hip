@@ -454,6 +454,65 @@ __device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, lon
   });
 }
 
+// Cells of a box whose membership in a ball of squared radius r2 can differ
+// between an old and a new centre, row by row (one thread per x-row): from
+// each row's exact y and z offsets, the x-chord of each ball widened by 1e-3
+// and its sure inside narrowed by 1e-3 (rounding moves a chord's end by far
+// less); the cells of the union of the two chords outside the common sure
+// inside are visited, where visit(ii, jj, kk) applies the exact test.  The box
+// (ext rows of slab sl = b, b + ZB, ...) is in coordinates unwrapped around
+// its centre, in which the old and new centres have x = cx[0] and cx[1]; a
+// box that nearly spans a periodic x axis has each of its cells visited.
+template <typename F>
+__device__ __forceinline__ void chord_changes(const DevDomain& d, const Box& bx, int b, int ZB, const double* xo,
+                                              const double* xn, const double* cx, double r2, F visit) {
+  constexpr double EPS = 1e-3;
+  const int nsl = b < bx.ext[2] ? (bx.ext[2] - 1 - b) / ZB + 1 : 0;
+  const int nrows = bx.ext[1] * nsl;
+  const bool whole_x = !d.walls[0] && bx.ext[0] + 2 > d.nx;
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    const int ty = r % bx.ext[1], sl = b + ZB * (r / bx.ext[1]);
+    const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
+    const int kk = d.walls[2] ? bx.lo[2] + sl : wrap_near(bx.lo[2] + sl, d.nz);
+    // the cells to visit, as x indices of the box: [s0, e0] and [s1, e1]
+    int s0 = 0, e0 = bx.ext[0] - 1, s1 = 1, e1 = 0;
+    if (!whole_x) {
+      int us = bx.ext[0], ue = -1, is = 0, ie = bx.ext[0] - 1;
+      for (int k = 0; k < 2; ++k) {
+        const double* c = k ? xn : xo;
+        const double dy = min_image(((double)jj + 0.5) - c[1], d.ny, d.walls[1]);
+        const double dz = min_image(((double)kk + 0.5) - c[2], d.nz, d.walls[2]);
+        const double rho = r2 - (dy * dy + dz * dz);
+        if (rho >= -EPS) {
+          const double a = sqrt(fmax(rho, 0.0)) + EPS;
+          us = min(us, (int)ceil(cx[k] - a - 0.5) - bx.lo[0]);
+          ue = max(ue, (int)floor(cx[k] + a - 0.5) - bx.lo[0]);
+        }
+        // sure inside: |g + 0.5 - cx| < a_in, i.e. g in [floor(cx - a_in - 0.5) + 1, ceil(cx + a_in - 0.5) - 1]
+        const double ain = rho > 0.0 ? sqrt(rho) - EPS : -1.0;
+        if (ain > 0.0) {
+          is = max(is, (int)floor(cx[k] - ain - 0.5) + 1 - bx.lo[0]);
+          ie = min(ie, (int)ceil(cx[k] + ain - 0.5) - 1 - bx.lo[0]);
+        } else {
+          is = 1, ie = 0;
+        }
+      }
+      s0 = max(us, 0);
+      e0 = min(ue, bx.ext[0] - 1);
+      if (is <= ie) {  // both balls surely hold [is, ie]
+        s1 = max(s0, ie + 1);
+        e1 = e0;
+        e0 = min(e0, is - 1);
+      }
+    }
+    for (int seg = 0; seg < 2; ++seg) {
+      const int gs = seg ? s1 : s0, ge = seg ? e1 : e0;
+      for (int g = gs; g <= ge; ++g)
+        visit(d.walls[0] ? bx.lo[0] + g : wrap_near(bx.lo[0] + g, d.nx), jj, kk);
+    }
+  }
+}
+
 constexpr int RECON_LIST = 1024;
 
 template <typename T>
@@ -476,13 +535,10 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
     R2 = R * R;
   }
   // A cell leaves sphere i only if its centre was inside the old ball and is
-  // outside the new one: the same FP64 test both mappings made, so only this
-  // thin shell of cells touches memory.  Cells to rebuild are listed in LDS
-  // and then rebuilt one wavefront each.  One thread per x-row of the box
-  // applies that test only where it can hold: on the cells within 1e-3 of the
-  // old ball's chord of the row that do not lie more than 1e-3 inside the new
-  // ball's chord (rounding moves a chord's end by far less), i.e. near its two
-  // ends; a box that spans a whole periodic x axis is scanned cell by cell.
+  // outside the new one: the same FP64 test both mappings made, applied to
+  // the cells near the ends of the balls' row chords, so only this thin shell
+  // of cells touches memory.  Cells to rebuild are listed in LDS and then
+  // rebuilt one wavefront each.
   auto visit = [&](int ii, int jj, int kk) {
     if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
       const long long c = cidx(d, ii, jj, kk);
@@ -498,46 +554,9 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
       }
     }
   };
-  constexpr double EPS = 1e-3;
-  const int nsl = b < bx.ext[2] ? (bx.ext[2] - 1 - b) / d.ZB + 1 : 0;
-  const int nrows = bx.ext[1] * nsl;
-  const bool whole_x = !d.walls[0] && bx.ext[0] >= d.nx;
-  // the new centre's x next to the old one (the box's coordinates are not
-  // wrapped: the old centre's offsets in them are the minimum images)
-  const double xn0 = xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0]);
-  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
-    const int ty = r % bx.ext[1], sl = b + d.ZB * (r / bx.ext[1]);
-    const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
-    const int kk = d.walls[2] ? bx.lo[2] + sl : wrap_near(bx.lo[2] + sl, d.nz);
-    const int g0 = bx.lo[0], g1 = bx.lo[0] + bx.ext[0] - 1;
-    // the cells to test: [s0, e0] and [s1, e1]
-    int s0 = g0, e0 = g1, s1 = 1, e1 = 0;
-    if (!whole_x) {
-      const double oy = min_image(((double)jj + 0.5) - xo[1], d.ny, d.walls[1]);
-      const double oz = min_image(((double)kk + 0.5) - xo[2], d.nz, d.walls[2]);
-      const double ro = R2 - (oy * oy + oz * oz);
-      const double ao = sqrt(fmax(ro, 0.0)) + EPS;
-      const double ny_ = min_image(((double)jj + 0.5) - xn[1], d.ny, d.walls[1]);
-      const double nz_ = min_image(((double)kk + 0.5) - xn[2], d.nz, d.walls[2]);
-      const double rn = R2 - (ny_ * ny_ + nz_ * nz_);
-      const double an = rn > 0.0 ? sqrt(rn) - EPS : -1.0;  // cells closer are inside
-      // cell g's centre is g + 0.5: the old chord covers [s0, e0] (none when
-      // the row misses the old ball); the sure inside of the new one, cells
-      // with |g + 0.5 - xn0| < an, is [C, D] (none when an <= 0)
-      s0 = max(g0, (int)ceil(xo[0] - ao - 0.5));
-      e0 = ro < -EPS ? s0 - 1 : min(g1, (int)floor(xo[0] + ao - 0.5));
-      if (an > 0.0) {
-        const int C = (int)floor(xn0 - an - 0.5) + 1, D = (int)ceil(xn0 + an - 0.5) - 1;
-        s1 = max(s0, D + 1);
-        e1 = e0;
-        e0 = min(e0, C - 1);
-      }
-    }
-    for (int seg = 0; seg < 2; ++seg) {
-      const int gs = seg ? s1 : s0, ge = seg ? e1 : e0;
-      for (int g = gs; g <= ge; ++g) visit(d.walls[0] ? g : wrap_near(g, d.nx), jj, kk);
-    }
-  }
+  // the box is unwrapped around the old centre
+  const double cx[2] = {xo[0], xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0])};
+  chord_changes(d, bx, b, d.ZB, xo, xn, cx, R2, visit);
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -871,6 +890,18 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step, int ad
 // sphere's solid cells that have a non-own neighbour are listed, and their
 // links are formed as in k_commit.  Dynamic LDS: edge^3 state bytes plus the
 // surface list.
+// mapping bin of a position
+__device__ __forceinline__ int mbin_index(const DevDomain& d, const double* x, int* b) {
+  const int n[3] = {d.nx, d.ny, d.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int nb = d.mbins.n[a];
+    const int k = (int)floor(x[a] * (double)nb / (double)n[a]);
+    b[a] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
+  }
+  return b[0] + d.mbins.n[0] * (b[1] + d.mbins.n[1] * b[2]);
+}
+
 constexpr uint8_t L_UNSET = 5;  // cell outside the staged ball
 
 
@@ -967,7 +998,6 @@ __device__ __forceinline__ void ball_links(const DevDomain& d, T* buf, size_t N,
 template <typename T>
 __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int i) {
   const int cur = map_buffer(d.ctl, in_step);
-  const uint32_t stamp = map_stamp(d.ctl);
   T* buf = (T*)d.pdf[cur];
   const size_t N = (size_t)d.N;
   extern __shared__ uint8_t smem[];
@@ -978,33 +1008,36 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   uint32_t* lk = reinterpret_cast<uint32_t*>(smem + ((NS + 15) & ~15) + ((2 * d.list_cap + 15) & ~15));
   __shared__ double red[6][4];
   const double xp[3] = {d.p.x[3 * i], d.p.x[3 * i + 1], d.p.x[3 * i + 2]};
-  const double xo[3] = {d.p.xmap[3 * i], d.p.xmap[3 * i + 1], d.p.xmap[3 * i + 2]};
   const double up[3] = {d.p.u[3 * i], d.p.u[3 * i + 1], d.p.u[3 * i + 2]};
   const double wp[3] = {d.p.w[3 * i], d.p.w[3 * i + 1], d.p.w[3 * i + 2]};
   const double R = d.p.R[i];
-  double rs2, rl2;
+  double rl2;
   {
 #pragma clang fp contract(off)
-    const double rs = R + d.delta_ab, rl = R + 3.0;
-    rs2 = rs * rs;
+    const double rl = R + 3.0;
     rl2 = rl * rl;
   }
   const int n[3] = {d.nx, d.ny, d.nz};
   bool finite = isfinite(xp[0]) && isfinite(xp[1]) && isfinite(xp[2]);
   int lo[3];
   for (int a = 0; a < 3; ++a) lo[a] = finite ? (int)floor(xp[a]) - H : 0;
+  // the mapping bins were last read by the mapping update before this launch:
+  // emptied here for the next step
+  if (in_step && finite && threadIdx.x == 0) {
+    int b[3];
+    d.mbins.cell[(size_t)mbin_index(d, xp, b) * (1 + BIN_CAP)] = 0;
+  }
 
-  // Row chords, kept in the link list's LDS (unused until step 4): of each
-  // x-row of a box, the cells whose centres can lie within a radius of a
-  // centre are those with x index in [s, e] (packed s | e << 16; s > e: none),
-  // from the row's exact y and z offsets, widened by 1e-3, far more than
-  // rounding moves a chord's end; the exact tests then run on those cells
-  // only.  Rows of a box that nearly spans a periodic x axis keep every cell.
+  // Row chords, kept in the link list's LDS (unused until step 3): of each
+  // x-row of the staged cube, the cells whose centres can lie within R + 3 of
+  // the centre are those with x index in [s, e] (packed s | e << 16; s > e:
+  // none), from the row's exact y and z offsets, widened by 1e-3.  Rows of a
+  // cube that nearly spans a periodic x axis keep every cell.
   constexpr double EPS = 1e-3;
   constexpr int CH = (Q - 1) * BALL_THREADS;
   uint32_t* chord = lk;
-  const bool chorded1 = he * he <= CH && (d.walls[0] || he + 2 <= n[0]);
-  if (chorded1) {
+  const bool chorded = he * he <= CH && (d.walls[0] || he + 2 <= n[0]);
+  if (chorded) {
     for (int r = threadIdx.x; r < he * he; r += blockDim.x) {
       const int gy = lo[1] + r % he, gz = lo[2] + r / he;
       const int jj = d.walls[1] ? gy : wrap_near(gy, n[1]), kk = d.walls[2] ? gz : wrap_near(gz, n[2]);
@@ -1019,15 +1052,15 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     __syncthreads();
   }
 
-  // 1. stage: eight cells per thread and pass, all loads issued before use;
-  // the cells within R + 3 of the centre (those of the row chords) are
-  // loaded: every link's y - c_q and y - 2 c_q lies within R + 2 sqrt(2)
+  // 1. stage the states of the cells within R + 3 of the centre (every
+  // link's y - c_q and y - 2 c_q lies within R + 2 sqrt(2)), from the flags
+  // and owners the mapping update has just written; eight cells per thread
+  // and pass, all loads issued before use
   for (int t0 = threadIdx.x; t0 < NS; t0 += 8 * blockDim.x) {
     long long cc[8];
     uint8_t code[8], fl[8];
-    unsigned long long kc[8];
+    int ow[8];
     bool ld[8];
-    uint32_t shell = 0u;  // bit u: within R + delta_aB of the centre
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * blockDim.x;
@@ -1049,11 +1082,10 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
           code[u] = L_WALL;
         } else {
           const int hx = t % he;
-          const uint32_t ch = chorded1 ? chord[t / he] : 0xFFFF0000u;
+          const uint32_t ch = chorded ? chord[t / he] : 0xFFFF0000u;
           if (hx >= (int)(ch & 0xFFFFu) && hx <= (int)(ch >> 16)) {
             cc[u] = cidx(d, ijk[0], ijk[1], ijk[2]);
             ld[u] = true;
-            if (cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) shell |= 1u << u;
           }
         }
       }
@@ -1062,107 +1094,26 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     for (int u = 0; u < 8; ++u)
       if (ld[u]) {
         fl[u] = d.flags[cc[u]];
-        kc[u] = d.claim[cc[u]];
+        ow[u] = d.owner[cc[u]];
       }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * blockDim.x;
       if (t >= NS) continue;
       if (ld[u]) {
-        if (fl[u] & F_WALL) {
+        if (fl[u] & F_WALL)
           code[u] = L_WALL;
-        } else if ((uint32_t)(kc[u] >> 32) == stamp) {
-          code[u] = (int)(0xFFFFFFFFu - (uint32_t)(kc[u] & 0xFFFFFFFFull)) == i ? L_OWN : L_OTHER;
-        } else {
-          // fluid: in this sphere's shell by the claims' own test on the same
-          // position; farther out the shells of other spheres are not known
-          // here (L_FLUID), and step 2 reads the shell stamp where it needs it
-          code[u] = (shell >> u) & 1u ? L_SHELL : L_FLUID;
-        }
+        else if (fl[u] & F_SOLID)
+          code[u] = ow[u] == i ? L_OWN : L_OTHER;
+        else
+          code[u] = L_FLUID;  // fluid, in a TRT+aB shell or not
       }
-      // bits 3-5: the flag byte loaded (at most 7), bit 6: none loaded
-      st[t] = code[u] | (ld[u] ? (uint8_t)(fl[u] << 3) : (uint8_t)0x40);
+      st[t] = code[u];
     }
   }
   __syncthreads();
 
-  // 2. flags and owners of the cells in the old and new shell balls; a cell
-  // claimed by another sphere is committed by that sphere's block
-  Box bx;
-  sphere_box(d, i, true, bx);
-  const int nbox = bx.ext[0] * bx.ext[1] * bx.ext[2];
-  // row chords of the union of the two shell balls (the box's x frame is
-  // unwrapped around the new centre)
-  const bool chorded2 = bx.ext[1] * bx.ext[2] <= CH && (d.walls[0] || bx.ext[0] + 2 <= n[0]);
-  if (chorded2) {
-    const double cx[2] = {xp[0], xp[0] + min_image(xo[0] - xp[0], n[0], d.walls[0])};
-    for (int r = threadIdx.x; r < bx.ext[1] * bx.ext[2]; r += blockDim.x) {
-      const int gy = bx.lo[1] + r % bx.ext[1], gz = bx.lo[2] + r / bx.ext[1];
-      const int jj = d.walls[1] ? gy : wrap_near(gy, n[1]), kk = d.walls[2] ? gz : wrap_near(gz, n[2]);
-      int s0 = bx.ext[0], e0 = -1;
-      for (int k = 0; k < 2; ++k) {
-        const double* cc = k ? xo : xp;
-        const double dy = min_image(((double)jj + 0.5) - cc[1], n[1], d.walls[1]);
-        const double dz = min_image(((double)kk + 0.5) - cc[2], n[2], d.walls[2]);
-        const double rho = rs2 - (dy * dy + dz * dz);
-        if (rho < -EPS) continue;
-        const double a = sqrt(fmax(rho, 0.0)) + EPS;
-        s0 = min(s0, (int)ceil(cx[k] - a - 0.5) - bx.lo[0]);
-        e0 = max(e0, (int)floor(cx[k] + a - 0.5) - bx.lo[0]);
-      }
-      s0 = max(s0, 0);
-      e0 = min(e0, bx.ext[0] - 1);
-      if (e0 < s0) s0 = 1, e0 = 0;
-      chord[r] = (uint32_t)s0 | ((uint32_t)e0 << 16);
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nbox; t += blockDim.x) {
-    const int tx = t % bx.ext[0], ty = (t / bx.ext[0]) % bx.ext[1], tz = t / (bx.ext[0] * bx.ext[1]);
-    if (chorded2) {
-      const uint32_t ch = chord[ty + bx.ext[1] * tz];
-      if (tx < (int)(ch & 0xFFFFu) || tx > (int)(ch >> 16)) continue;
-    }
-    const int g[3] = {bx.lo[0] + tx, bx.lo[1] + ty, bx.lo[2] + tz};
-    int ijk[3], h[3];
-    bool in = true;
-    for (int a = 0; a < 3; ++a) {
-      ijk[a] = d.walls[a] ? g[a] : wrap_near(g[a], n[a]);
-      h[a] = g[a] - lo[a];
-      if (!d.walls[a] && (h[a] < 0 || h[a] >= he)) h[a] = wrapmod(h[a], n[a]);
-      in = in && h[a] >= 0 && h[a] < he;
-    }
-    if (!(cell_d2(d, ijk[0], ijk[1], ijk[2], xp) <= rs2) && !(cell_d2(d, ijk[0], ijk[1], ijk[2], xo) <= rs2))
-      continue;
-    const long long c = cidx(d, ijk[0], ijk[1], ijk[2]);
-    const uint8_t sv = in ? st[h[0] + he * (h[1] + he * h[2])] : (uint8_t)(L_UNSET | 0x40);
-    const uint8_t sc = sv & 7, of = sv >> 3;  // of = 8: no flag byte loaded
-    if (sc == L_WALL || sc == L_OTHER) continue;
-    uint8_t nf;
-    int no = -1;
-    if (sc == L_OWN) {
-      nf = F_SOLID;
-      no = i;
-    } else if (sc == L_SHELL) {
-      nf = F_SHELL;
-    } else if (sc == L_FLUID) {  // only in the shell of the old position
-      nf = d.shellstamp[c] == stamp ? F_SHELL : (uint8_t)0;
-    } else {
-      const int ns = new_state(d, c, stamp, &no);
-      if (ns == S_WALL) continue;
-      nf = ns == S_SOLID ? F_SOLID : (ns == S_SHELL ? F_SHELL : (uint8_t)0);
-      if (ns != S_SOLID) no = -1;
-    }
-    // every block that commits a cell stores the same byte, so one that
-    // loaded the new byte already may skip it
-    if (of != nf) d.flags[c] = nf;
-    if (no >= 0) d.owner[c] = no;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < NS; t += blockDim.x) st[t] &= 7;
-  __syncthreads();
-
-  // 3. solid cells of this sphere with a neighbour that is not, listed in
+  // 2. solid cells of this sphere with a neighbour that is not, listed in
   // cube order (ordered compaction: wavefront ballots and per-wave offsets),
   // so that every cell is summed by the same thread on every run.  Only the
   // central box of edge 2 ceil(R) + 3 can hold cells of this sphere (their
@@ -1194,7 +1145,7 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   }
   __syncthreads();
 
-  // 4. links: the listed cells in chunks of one cell per thread; a chunk's
+  // 3. links: the listed cells in chunks of one cell per thread; a chunk's
   // links (y, q) with y - c_q not this sphere's solid are listed direction by
   // direction, cells in order within a direction (ordered compaction), then
   // shared out over all threads: a wavefront's loads then walk neighbouring
@@ -1236,7 +1187,7 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
       ball_links<T, BALL_LINK_UNROLL>(d, buf, N, st, lk, k0, tot, he, lo, xp, up, wp, R, acc);
     __syncthreads();  // the next chunk reuses the list and the wave sums
   }
-  // 5. fixed-order block reduction
+  // 4. fixed-order block reduction
   for (int k = 0; k < 6; ++k) {
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -1266,52 +1217,9 @@ __global__ __launch_bounds__(BALL_THREADS) __attribute__((amdgpu_waves_per_eu(5,
 }
 
 
-void launch_claim(const DevDomain& d, int in_step, bool lists, hipStream_t s) {
+static void launch_claim(const DevDomain& d, int in_step, bool lists, hipStream_t s) {
   const int nsb = d.P * d.ZB;
   if (nsb > 0) hipLaunchKernelGGL(k_claim, dim3(nsb), dim3(256), 0, s, d, in_step, (in_step && lists) ? 1 : 0);
-}
-
-template <typename T>
-static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
-  const int nsb = d.P * d.ZB;
-  if (nsb <= 0) {
-    if (advance) launch_advance(d, s);
-    return;
-  }
-  if (reconstruct) hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, in_step);
-  // The step control rides on the last block only where the launch has few
-  // blocks: the count of finished blocks is one device-wide atomic per block,
-  // which costs more than the saved launch once there are thousands.
-  const int blocks = d.map_ball ? xcd_grid(d.P) : nsb * d.RB;
-  const int fold = advance && blocks <= FOLD_ADVANCE_MAX_BLOCKS;
-  if (d.map_ball) {
-    hipLaunchKernelGGL(k_commit_ball<T>, dim3(blocks), dim3(BALL_THREADS), ball_lds_bytes(d.stage_edge, d.list_cap), s, d,
-                       in_step, fold);
-  } else {
-    hipLaunchKernelGGL(k_commit<T>, dim3(blocks), dim3(256), 0, s, d, in_step, fold);
-  }
-  if (advance && !fold) launch_advance(d, s);
-}
-
-static void launch_update_any(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
-  if (d.storage == 0)
-    launch_update_t<double>(d, reconstruct, in_step, advance, s);
-  else if (d.storage == 1)
-    launch_update_t<float>(d, reconstruct, in_step, advance, s);
-  else
-    launch_update_t<__half>(d, reconstruct, in_step, advance, s);
-}
-
-void launch_update(const DevDomain& d, bool reconstruct, int in_step, hipStream_t s) {
-  launch_update_any(d, reconstruct, in_step, 0, s);
-}
-
-void launch_update_and_advance(const DevDomain& d, hipStream_t s) { launch_update_any(d, true, 1, 1, s); }
-
-void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
-  launch_claim(d, 0, false, s);
-  launch_update(d, reconstruct, 0, s);
-  hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
 }
 
 // ---- geometric mapping of the fused step ------------------------------------
@@ -1329,16 +1237,6 @@ void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
 // value.  Outside a step (new, moved or restored spheres) every cell is
 // evaluated.
 
-__device__ __forceinline__ int mbin_index(const DevDomain& d, const double* x, int* b) {
-  const int n[3] = {d.nx, d.ny, d.nz};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int nb = d.mbins.n[a];
-    const int k = (int)floor(x[a] * (double)nb / (double)n[a]);
-    b[a] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
-  }
-  return b[0] + d.mbins.n[0] * (b[1] + d.mbins.n[1] * b[2]);
-}
 
 // insert (clear = 0) or remove (clear = 1: zero the count of its bin) every
 // sphere by its current position
@@ -1410,25 +1308,6 @@ __device__ __forceinline__ bool wall_cell(const DevDomain& d, int i, int j, int 
          (d.walls[2] && (k == 0 || k == d.nz - 1));
 }
 
-// Rows of a box for the geometric mapping kernels: groups of 32 threads take
-// the (y, z) rows in turn and cover a row in steps of 32 cells.  Per row the
-// squared y and z offsets from a centre are formed once; per cell then
-// (dx dx + dy dy) + dz dz, the same rounding as cell_d2.
-struct RowPos {
-  double dy2, dz2;
-};
-__device__ __forceinline__ RowPos row_pos(const DevDomain& d, int jj, int kk, const double* xp) {
-#pragma clang fp contract(off)
-  const double dy = min_image(((double)jj + 0.5) - xp[1], d.ny, d.walls[1]);
-  const double dz = min_image(((double)kk + 0.5) - xp[2], d.nz, d.walls[2]);
-  return RowPos{dy * dy, dz * dz};
-}
-__device__ __forceinline__ double row_d2(const DevDomain& d, int ii, const RowPos& r, const double* xp) {
-#pragma clang fp contract(off)
-  const double dx = min_image(((double)ii + 0.5) - xp[0], d.nx, d.walls[0]);
-  return (dx * dx + r.dy2) + r.dz2;
-}
-
 // Reconstruction inside a step (one block per sphere i): cells of i's solid
 // at the mapped positions (flags and owners in place) that are not solid at
 // the new positions, from neighbours fluid before (flags) and after
@@ -1457,30 +1336,22 @@ __global__ __launch_bounds__(256) void k_recon_geo(DevDomain d) {
     int o;
     return !(d.flags[y] & (F_SOLID | F_WALL)) && geo_state(d, yi, yj, yk, &o) != S_SOLID;
   };
-  {
-    const int col = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-    for (int r = grp; r < bx.ext[1] * bx.ext[2]; r += ngrp) {
-      const int ty = r % bx.ext[1], tz = r / bx.ext[1];
-      const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
-      const int kk = d.walls[2] ? bx.lo[2] + tz : wrap_near(bx.lo[2] + tz, d.nz);
-      const RowPos po = row_pos(d, jj, kk, xo), pn = row_pos(d, jj, kk, xn);
-      if (po.dy2 + po.dz2 > R2) continue;  // the row misses the old ball
-      for (int tx = col; tx < bx.ext[0]; tx += 32) {
-        const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
-        if (row_d2(d, ii, po, xo) <= R2 && !(row_d2(d, ii, pn, xn) <= R2)) {
-          const long long c = cidx(d, ii, jj, kk);
-          int o;
-          if ((d.flags[c] & F_SOLID) && d.owner[c] == i && geo_state(d, ii, jj, kk, &o) != S_SOLID) {
-            const int k = atomicAdd(&ncand, 1);
-            if (k < RECON_LIST)
-              cand[k] = c;
-            else
-              reconstruct_with<T>(d, buf, ii, jj, kk, i, usable);  // list full: rebuild here
-          }
-        }
+  auto visit = [&](int ii, int jj, int kk) {
+    if (cell_d2(d, ii, jj, kk, xo) <= R2 && !(cell_d2(d, ii, jj, kk, xn) <= R2)) {
+      const long long c = cidx(d, ii, jj, kk);
+      int o;
+      if ((d.flags[c] & F_SOLID) && d.owner[c] == i && geo_state(d, ii, jj, kk, &o) != S_SOLID) {
+        const int k = atomicAdd(&ncand, 1);
+        if (k < RECON_LIST)
+          cand[k] = c;
+        else
+          reconstruct_with<T>(d, buf, ii, jj, kk, i, usable);  // list full: rebuild here
       }
     }
-  }
+  };
+  // the box is unwrapped around the old centre
+  const double cx[2] = {xo[0], xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0])};
+  chord_changes(d, bx, 0, 1, xo, xn, cx, R2, visit);
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -1506,29 +1377,25 @@ __global__ __launch_bounds__(256) void k_remap_geo(DevDomain d) {
     R2 = R * R;
     rs2 = rs * rs;
   }
-  const int col = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-  for (int r = grp; r < bx.ext[1] * bx.ext[2]; r += ngrp) {
-    const int ty = r % bx.ext[1], tz = r / bx.ext[1];
-    const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
-    const int kk = d.walls[2] ? bx.lo[2] + tz : wrap_near(bx.lo[2] + tz, d.nz);
-    if ((d.walls[1] && (jj == 0 || jj == d.ny - 1)) || (d.walls[2] && (kk == 0 || kk == d.nz - 1))) continue;
-    const RowPos po = row_pos(d, jj, kk, xo), pn = row_pos(d, jj, kk, xn);
-    if (po.dy2 + po.dz2 > rs2 && pn.dy2 + pn.dz2 > rs2) continue;  // the row misses both shell balls
-    for (int tx = col; tx < bx.ext[0]; tx += 32) {
-      const int ii = d.walls[0] ? bx.lo[0] + tx : wrap_near(bx.lo[0] + tx, d.nx);
-      if (d.walls[0] && (ii == 0 || ii == d.nx - 1)) continue;
-      const double d2o = row_d2(d, ii, po, xo), d2n = row_d2(d, ii, pn, xn);
-      if ((d2o <= R2) != (d2n <= R2) || (d2o <= rs2) != (d2n <= rs2)) {
-        int own;
-        const int st = geo_state(d, ii, jj, kk, &own);
-        const long long c = cidx(d, ii, jj, kk);
-        const uint8_t fl = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
-        d.flags[c] = fl;
-        if (st == S_SOLID) d.owner[c] = own;
-        d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (uint32_t)(own + 1) << 8 : 0u);
-      }
+  // the cells where i's solid or shell membership changed lie near the ends
+  // of the row chords of its old and new balls of radius R and R + delta_aB
+  auto visit = [&](int ii, int jj, int kk) {
+    if (wall_cell(d, ii, jj, kk)) return;
+    const double d2o = cell_d2(d, ii, jj, kk, xo), d2n = cell_d2(d, ii, jj, kk, xn);
+    if ((d2o <= R2) != (d2n <= R2) || (d2o <= rs2) != (d2n <= rs2)) {
+      int own;
+      const int st = geo_state(d, ii, jj, kk, &own);
+      const long long c = cidx(d, ii, jj, kk);
+      const uint8_t fl = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
+      d.flags[c] = fl;
+      if (st == S_SOLID) d.owner[c] = own;
+      if (d.cellw) d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (uint32_t)(own + 1) << 8 : 0u);
     }
-  }
+  };
+  // the box is unwrapped around the new centre
+  const double cx[2] = {xn[0] + min_image(xo[0] - xn[0], d.nx, d.walls[0]), xn[0]};
+  chord_changes(d, bx, 0, 1, xo, xn, cx, R2, visit);
+  chord_changes(d, bx, 0, 1, xo, xn, cx, rs2, visit);
 }
 
 // End of a fused step: the mapping bins are emptied (by the positions they
@@ -1588,7 +1455,7 @@ __global__ void k_commit_full(DevDomain d) {
     const uint8_t fl = st == S_SOLID ? F_SOLID : (st == S_SHELL ? F_SHELL : (uint8_t)0);
     d.flags[c] = fl;
     if (st == S_SOLID) d.owner[c] = (int)(v >> 2) - 1;
-    d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (v >> 2) << 8 : 0u);
+    if (d.cellw) d.cellw[c] = (uint32_t)fl | (st == S_SOLID ? (v >> 2) << 8 : 0u);
   }
 }
 
@@ -1597,7 +1464,7 @@ static dim3 cells_grid(long long N) {
   return dim3((unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b)));
 }
 
-void launch_mapping_fused(const DevDomain& d, bool reconstruct, hipStream_t s) {
+void launch_mapping_geo(const DevDomain& d, bool reconstruct, hipStream_t s) {
   const dim3 gp((unsigned)((d.P + 255) / 256 > 0 ? (d.P + 255) / 256 : 1));
   if (d.P > 0) hipLaunchKernelGGL(k_mbins, gp, dim3(256), 0, s, d, 0, 0);
   hipLaunchKernelGGL(k_geo_stage, cells_grid(d.N), dim3(256), 0, s, d);
@@ -1626,6 +1493,74 @@ void launch_update_fused(const DevDomain& d, hipStream_t s) {
     hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(256), 0, s, d);
   }
   hipLaunchKernelGGL(k_advance_fused, dim3(gp), dim3(256), 0, s, d);
+}
+
+// ---- mapping update and boundary values ------------------------------------
+// Slab pass (few spheres): claims, then reconstruction and the commit with
+// the boundary values from the claims.  Ball pass (many spheres): the
+// geometric update of flags and owners (the kernels above, from the mapping
+// bins), then the boundary values from the flags and owners.
+
+void launch_map_prepare(const DevDomain& d, bool lists, hipStream_t s) {
+  if (!d.map_ball) {
+    launch_claim(d, 1, lists, s);
+    return;
+  }
+  const unsigned gp = (unsigned)((d.P + 255) / 256 > 0 ? (d.P + 255) / 256 : 1);
+  if (d.P > 0) hipLaunchKernelGGL(k_mbins, dim3(gp), dim3(256), 0, s, d, 1, 0);
+}
+
+template <typename T>
+static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
+  const int nsb = d.P * d.ZB;
+  if (nsb <= 0) {
+    if (advance) launch_advance(d, s);
+    return;
+  }
+  if (d.map_ball) {
+    // inside a step: reconstruction and the flags and owners of the new
+    // positions (outside, launch_mapping has updated them)
+    if (in_step) {
+      if (reconstruct) hipLaunchKernelGGL(k_recon_geo<T>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(256), 0, s, d);
+    }
+  } else if (reconstruct) {
+    hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, in_step);
+  }
+  // The step control rides on the last block only where the launch has few
+  // blocks: the count of finished blocks is one device-wide atomic per block,
+  // which costs more than the saved launch once there are thousands.
+  const int blocks = d.map_ball ? xcd_grid(d.P) : nsb * d.RB;
+  const int fold = advance && blocks <= FOLD_ADVANCE_MAX_BLOCKS;
+  if (d.map_ball) {
+    hipLaunchKernelGGL(k_commit_ball<T>, dim3(blocks), dim3(BALL_THREADS), ball_lds_bytes(d.stage_edge, d.list_cap), s, d,
+                       in_step, fold);
+  } else {
+    hipLaunchKernelGGL(k_commit<T>, dim3(blocks), dim3(256), 0, s, d, in_step, fold);
+  }
+  if (advance && !fold) launch_advance(d, s);
+}
+
+static void launch_update_any(const DevDomain& d, bool reconstruct, int in_step, int advance, hipStream_t s) {
+  if (d.storage == 0)
+    launch_update_t<double>(d, reconstruct, in_step, advance, s);
+  else if (d.storage == 1)
+    launch_update_t<float>(d, reconstruct, in_step, advance, s);
+  else
+    launch_update_t<__half>(d, reconstruct, in_step, advance, s);
+}
+
+void launch_update_and_advance(const DevDomain& d, hipStream_t s) { launch_update_any(d, true, 1, 1, s); }
+
+void launch_mapping(const DevDomain& d, bool reconstruct, hipStream_t s) {
+  if (d.map_ball) {
+    launch_mapping_geo(d, reconstruct, s);
+    launch_update_any(d, false, 0, 0, s);
+  } else {
+    launch_claim(d, 0, false, s);
+    launch_update_any(d, reconstruct, 0, 0, s);
+  }
+  hipLaunchKernelGGL(k_new_stamp, dim3(1), dim3(1), 0, s, d.ctl);
 }
 
 // ---- batched mapping update (slab blocks; one launch per kernel for all domains)
