@@ -176,9 +176,14 @@ Layout make_layout(const lbmdem_config& c) {
   L.pdf1 = take((size_t)Q * N * sz);
   L.flags = take(N);
   L.owner = take(4 * N);
-  L.claim = take(8 * N);
-  L.shellstamp = take(4 * N);
-  L.cellw = take(use_fused(c) ? 4 * N : 0);  // fused step: flags | (owner + 1) << 8
+  // claim words and shell stamps: the slab pass only (the ball pass and the
+  // fused step update flags and owners from the positions)
+  const bool claims = !use_ball(c) && !use_fused(c);
+  L.claim = take(claims ? 8 * N : 0);
+  L.shellstamp = take(claims ? 4 * N : 0);
+  // flags | (owner + 1) << 8 in one word, read by the fused sweep and the ball
+  // pass's staging
+  L.cellw = take(use_fused(c) || use_ball(c) ? 4 * N : 0);
   L.stage = take(8 * N);
   // fused step (tile slots) and geometric mapping (bins of the fused step and
   // the ball pass) only; transient, so not part of a checkpoint
@@ -546,9 +551,10 @@ int32_t lbmdem_create(const lbmdem_config* cfg, void* dev_buf, size_t dev_bytes,
   d.pdf[1] = base + L.pdf1;
   d.flags = (uint8_t*)(base + L.flags);
   d.owner = (int32_t*)(base + L.owner);
-  d.claim = (unsigned long long*)(base + L.claim);
-  d.shellstamp = (uint32_t*)(base + L.shellstamp);
-  d.cellw = use_fused(*cfg) ? (uint32_t*)(base + L.cellw) : nullptr;
+  const bool claims = !use_ball(*cfg) && !use_fused(*cfg);
+  d.claim = claims ? (unsigned long long*)(base + L.claim) : nullptr;
+  d.shellstamp = claims ? (uint32_t*)(base + L.shellstamp) : nullptr;
+  d.cellw = use_fused(*cfg) || use_ball(*cfg) ? (uint32_t*)(base + L.cellw) : nullptr;
   DevParticles& p = d.p;
   p.x = (double*)(base + L.x);
   p.u = (double*)(base + L.u);
@@ -1170,7 +1176,8 @@ bool same_config(const lbmdem_config& a, const lbmdem_config& b) {
 }
 
 // device segments of a checkpoint: the current PDF buffer, the cell arrays
-// (flags, owner, claims, shell stamps) and the particle block
+// (flags, owners and, where the domain has them, claims, shell stamps and
+// cell words) and the particle block
 void ck_segments(const lbmdem_domain* dom, int cur, char** at, size_t* len) {
   char* base = (char*)dom->region;
   const Layout& L = dom->L;

@@ -19,8 +19,10 @@ __global__ void k_init(DevDomain d) {
                       (d.walls[2] && (k == 0 || k == d.nz - 1));
     d.flags[c] = wall ? F_WALL : 0;
     d.owner[c] = -1;
-    d.claim[c] = 0ull;
-    d.shellstamp[c] = 0u;
+    if (d.claim) {
+      d.claim[c] = 0ull;
+      d.shellstamp[c] = 0u;
+    }
     if (d.cellw) d.cellw[c] = wall ? F_WALL : 0u;
     for (int q = 0; q < Q; ++q) {
       a[(size_t)q * N + c] = T(0.0f);

@@ -11,7 +11,9 @@
 //   owner       int32 per cell, sphere id of solid cells
 //   claim       uint64 per cell, (stamp << 32 | ~id) max-claim of the mapping
 //   shellstamp  uint32 per cell, stamp of the last mapping that put the cell
-//               inside some sphere's TRT+aB shell
+//               inside some sphere's TRT+aB shell (both for the slab pass
+//               only; null where the mapping bins serve: ball pass, fused
+//               step)
 //   particle SoA in FP64, per-(sphere, box-slab) force partials, contact
 //   history slots, neighbour lists and a device status word.
 #pragma once

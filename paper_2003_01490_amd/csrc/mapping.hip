@@ -454,18 +454,20 @@ __device__ void reconstruct_wave(const DevDomain& d, T* buf, uint32_t stamp, lon
   });
 }
 
-// Cells of a box whose membership in a ball of squared radius r2 can differ
-// between an old and a new centre, row by row (one thread per x-row): from
-// each row's exact y and z offsets, the x-chord of each ball widened by 1e-3
-// and its sure inside narrowed by 1e-3 (rounding moves a chord's end by far
-// less); the cells of the union of the two chords outside the common sure
-// inside are visited, where visit(ii, jj, kk) applies the exact test.  The box
-// (ext rows of slab sl = b, b + ZB, ...) is in coordinates unwrapped around
-// its centre, in which the old and new centres have x = cx[0] and cx[1]; a
-// box that nearly spans a periodic x axis has each of its cells visited.
-template <typename F>
+// Cells of a box whose membership in a ball of squared radius r2[m] (m <
+// NR, increasing) can differ between an old and a new centre, row by row
+// (one thread per x-row): from each row's exact y and z offsets, the x-chord
+// of each ball widened by 1e-3 and its sure inside narrowed by 1e-3 (rounding
+// moves a chord's end by far less); per radius the cells of the union of the
+// two chords outside the common sure inside are visited, where visit(ii, jj,
+// kk) applies the exact test (a cell near the chords of two radii is visited
+// twice).  The box (ext rows of slab sl = b, b + ZB, ...) is in coordinates
+// unwrapped around its centre, in which the old and new centres have x =
+// cx[0] and cx[1]; a box that nearly spans a periodic x axis has each of its
+// cells visited once.
+template <int NR, typename F>
 __device__ __forceinline__ void chord_changes(const DevDomain& d, const Box& bx, int b, int ZB, const double* xo,
-                                              const double* xn, const double* cx, double r2, F visit) {
+                                              const double* xn, const double* cx, const double* r2, F visit) {
   constexpr double EPS = 1e-3;
   const int nsl = b < bx.ext[2] ? (bx.ext[2] - 1 - b) / ZB + 1 : 0;
   const int nrows = bx.ext[1] * nsl;
@@ -474,41 +476,63 @@ __device__ __forceinline__ void chord_changes(const DevDomain& d, const Box& bx,
     const int ty = r % bx.ext[1], sl = b + ZB * (r / bx.ext[1]);
     const int jj = d.walls[1] ? bx.lo[1] + ty : wrap_near(bx.lo[1] + ty, d.ny);
     const int kk = d.walls[2] ? bx.lo[2] + sl : wrap_near(bx.lo[2] + sl, d.nz);
-    // the cells to visit, as x indices of the box: [s0, e0] and [s1, e1]
-    int s0 = 0, e0 = bx.ext[0] - 1, s1 = 1, e1 = 0;
-    if (!whole_x) {
-      int us = bx.ext[0], ue = -1, is = 0, ie = bx.ext[0] - 1;
+    // up to two segments [sa, ea] of box x indices per radius
+    int sa[2 * NR], ea[2 * NR];
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) sa[k] = 1, ea[k] = 0;
+    if (whole_x) {
+      sa[0] = 0;
+      ea[0] = bx.ext[0] - 1;
+    } else {
+      double yz[2];  // squared y-z offsets of the row from the two centres
+#pragma unroll
       for (int k = 0; k < 2; ++k) {
         const double* c = k ? xn : xo;
         const double dy = min_image(((double)jj + 0.5) - c[1], d.ny, d.walls[1]);
         const double dz = min_image(((double)kk + 0.5) - c[2], d.nz, d.walls[2]);
-        const double rho = r2 - (dy * dy + dz * dz);
-        if (rho >= -EPS) {
-          const double a = sqrt(fmax(rho, 0.0)) + EPS;
-          us = min(us, (int)ceil(cx[k] - a - 0.5) - bx.lo[0]);
-          ue = max(ue, (int)floor(cx[k] + a - 0.5) - bx.lo[0]);
-        }
-        // sure inside: |g + 0.5 - cx| < a_in, i.e. g in [floor(cx - a_in - 0.5) + 1, ceil(cx + a_in - 0.5) - 1]
-        const double ain = rho > 0.0 ? sqrt(rho) - EPS : -1.0;
-        if (ain > 0.0) {
-          is = max(is, (int)floor(cx[k] - ain - 0.5) + 1 - bx.lo[0]);
-          ie = min(ie, (int)ceil(cx[k] + ain - 0.5) - 1 - bx.lo[0]);
-        } else {
-          is = 1, ie = 0;
-        }
+        yz[k] = dy * dy + dz * dz;
       }
-      s0 = max(us, 0);
-      e0 = min(ue, bx.ext[0] - 1);
-      if (is <= ie) {  // both balls surely hold [is, ie]
-        s1 = max(s0, ie + 1);
-        e1 = e0;
-        e0 = min(e0, is - 1);
+#pragma unroll
+      for (int m = 0; m < NR; ++m) {
+        int us = bx.ext[0], ue = -1, is = 0, ie = bx.ext[0] - 1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const double rho = r2[m] - yz[k];
+          if (rho >= -EPS) {
+            const double a = sqrt(fmax(rho, 0.0)) + EPS;
+            us = min(us, (int)ceil(cx[k] - a - 0.5) - bx.lo[0]);
+            ue = max(ue, (int)floor(cx[k] + a - 0.5) - bx.lo[0]);
+          }
+          // sure inside: |g + 0.5 - cx| < a_in, i.e. g in
+          // [floor(cx - a_in - 0.5) + 1, ceil(cx + a_in - 0.5) - 1]
+          const double ain = rho > 0.0 ? sqrt(rho) - EPS : -1.0;
+          if (ain > 0.0) {
+            is = max(is, (int)floor(cx[k] - ain - 0.5) + 1 - bx.lo[0]);
+            ie = min(ie, (int)ceil(cx[k] + ain - 0.5) - 1 - bx.lo[0]);
+          } else {
+            is = 1, ie = 0;
+          }
+        }
+        const int s0 = max(us, 0), e0 = min(ue, bx.ext[0] - 1);
+        sa[2 * m] = s0;
+        ea[2 * m] = is <= ie ? min(e0, is - 1) : e0;  // both balls surely hold [is, ie]
+        sa[2 * m + 1] = is <= ie ? max(s0, ie + 1) : 1;
+        ea[2 * m + 1] = is <= ie ? e0 : 0;
       }
     }
-    for (int seg = 0; seg < 2; ++seg) {
-      const int gs = seg ? s1 : s0, ge = seg ? e1 : e0;
-      for (int g = gs; g <= ge; ++g)
-        visit(d.walls[0] ? bx.lo[0] + g : wrap_near(bx.lo[0] + g, d.nx), jj, kk);
+    // one loop over the cells of all segments, so that visit is inlined once
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * NR; ++k) tot += max(ea[k] - sa[k] + 1, 0);
+    for (int q = 0; q < tot; ++q) {
+      int g = 0, rem = q;
+#pragma unroll
+      for (int k = 0; k < 2 * NR; ++k) {
+        const int len = max(ea[k] - sa[k] + 1, 0);
+        if (rem >= 0 && rem < len) g = sa[k] + rem;
+        rem -= len;
+      }
+      visit(d.walls[0] ? bx.lo[0] + g : wrap_near(bx.lo[0] + g, d.nx), jj, kk);
     }
   }
 }
@@ -556,7 +580,7 @@ __device__ __forceinline__ void recon_block(const DevDomain& d, int blk, int cur
   };
   // the box is unwrapped around the old centre
   const double cx[2] = {xo[0], xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0])};
-  chord_changes(d, bx, b, d.ZB, xo, xn, cx, R2, visit);
+  chord_changes<1>(d, bx, b, d.ZB, xo, xn, cx, &R2, visit);
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -1053,13 +1077,13 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
   }
 
   // 1. stage the states of the cells within R + 3 of the centre (every
-  // link's y - c_q and y - 2 c_q lies within R + 2 sqrt(2)), from the flags
-  // and owners the mapping update has just written; eight cells per thread
-  // and pass, all loads issued before use
+  // link's y - c_q and y - 2 c_q lies within R + 2 sqrt(2)), from the cell
+  // words (flags | (owner + 1) << 8) the mapping update has just written;
+  // eight cells per thread and pass, all loads issued before use
   for (int t0 = threadIdx.x; t0 < NS; t0 += 8 * blockDim.x) {
     long long cc[8];
-    uint8_t code[8], fl[8];
-    int ow[8];
+    uint8_t code[8];
+    uint32_t cw[8];
     bool ld[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1092,19 +1116,16 @@ __device__ __forceinline__ void commit_ball(const DevDomain& d, int in_step, int
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (ld[u]) {
-        fl[u] = d.flags[cc[u]];
-        ow[u] = d.owner[cc[u]];
-      }
+      if (ld[u]) cw[u] = d.cellw[cc[u]];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * blockDim.x;
       if (t >= NS) continue;
       if (ld[u]) {
-        if (fl[u] & F_WALL)
+        if (cw[u] & F_WALL)
           code[u] = L_WALL;
-        else if (fl[u] & F_SOLID)
-          code[u] = ow[u] == i ? L_OWN : L_OTHER;
+        else if (cw[u] & F_SOLID)
+          code[u] = (int)(cw[u] >> 8) - 1 == i ? L_OWN : L_OTHER;
         else
           code[u] = L_FLUID;  // fluid, in a TRT+aB shell or not
       }
@@ -1351,7 +1372,7 @@ __global__ __launch_bounds__(256) void k_recon_geo(DevDomain d) {
   };
   // the box is unwrapped around the old centre
   const double cx[2] = {xo[0], xo[0] + min_image(xn[0] - xo[0], d.nx, d.walls[0])};
-  chord_changes(d, bx, 0, 1, xo, xn, cx, R2, visit);
+  chord_changes<1>(d, bx, 0, 1, xo, xn, cx, &R2, visit);
   __syncthreads();
   const int n = min(ncand, RECON_LIST);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -1394,8 +1415,8 @@ __global__ __launch_bounds__(256) void k_remap_geo(DevDomain d) {
   };
   // the box is unwrapped around the new centre
   const double cx[2] = {xn[0] + min_image(xo[0] - xn[0], d.nx, d.walls[0]), xn[0]};
-  chord_changes(d, bx, 0, 1, xo, xn, cx, R2, visit);
-  chord_changes(d, bx, 0, 1, xo, xn, cx, rs2, visit);
+  const double r2[2] = {R2, rs2};
+  chord_changes<2>(d, bx, 0, 1, xo, xn, cx, r2, visit);
 }
 
 // End of a fused step: the mapping bins are emptied (by the positions they
