@@ -194,7 +194,8 @@ def test_couette_channel_and_moving_walls():
     _compare_fields(g, o)
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere, fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_walls_on_all_axes(mk):
     n = (12, 11, 10)
     _case(f"closed box {n} map_kernel {mk}")
@@ -217,7 +218,8 @@ def test_walls_on_all_axes(mk):
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere, fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_mapping_bit_exact(storage, mk):
     n = (30, 28, 26)
     _case(f"mapping {n} storage {storage} map_kernel {mk}")
@@ -255,7 +257,9 @@ def test_mapping_bit_exact(storage, mk):
     assert co[10, 10, 15] == O.SOLID and og[10, 10, 15] == 0  # the shared tie cell
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), fused into the sweep (the domain is too
+# narrow for the one-block-per-sphere pass's staged cube)
+@pytest.mark.parametrize("mk", [0, 3])
 def test_fixed_sphere_forces_on_random_field(mk):
     n = (20, 18, 22)
     _case(f"fixed sphere forces {n} map_kernel {mk}")
@@ -300,7 +304,8 @@ def test_settling_sphere_32_fp64(seed, mk):
     _compare_fields(g, o, vel_rel=2e-10)
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere, fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_contact_variant_fp64(mk):
     """Contact and lubrication with the wall; the workgroup DEM kernel (LDS
     variant) and the one-thread-per-sphere one side by side."""
@@ -333,7 +338,8 @@ def test_contact_variant_fp64(mk):
         _compare_fields(g, o, vel_rel=5e-11)
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere, fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_two_spheres_oblique_collision_fp64(mk):
     n = (40, 24, 24)
     _case(f"two spheres colliding, periodic, DEM kernels 1 and 2, map_kernel {mk}")
@@ -366,7 +372,8 @@ def test_two_spheres_oblique_collision_fp64(mk):
         _compare_fields(g, o, vel_rel=1e-11)
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere, fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_prescribed_ramp_and_release(mk):
     n = (24, 24, 40)
     _case(f"prescribed ramp and release, map_kernel {mk}")
@@ -393,7 +400,9 @@ def test_prescribed_ramp_and_release(mk):
     _compare_fields(g, o, vel_rel=5e-12)
 
 
-@pytest.mark.parametrize("mk", [0, 3])  # boundary pass: automatic, fused into the sweep
+# boundary pass: automatic (slab), one block per sphere (geometric mapping
+# update; at 18^3 its staged cube keeps whole rows), fused into the sweep
+@pytest.mark.parametrize("mk", [0, 2, 3])
 def test_update_spheres_reconstructs(mk):
     n = (18, 18, 18)
     _case(f"teleport + reconstruction, map_kernel {mk}")
@@ -480,7 +489,7 @@ def _bitwise_equal(a, b):
     return all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("dem_kernel,mk", [(1, 0), (2, 0), (2, 3)])
+@pytest.mark.parametrize("dem_kernel,mk", [(1, 0), (2, 0), (2, 2), (2, 3)])
 def test_checkpoint_restore_bitwise(dem_kernel, mk):
     """Continuing from a checkpoint equals continuing the saved domain bit for
     bit (contact history, averaging memory, boundary values included)."""
