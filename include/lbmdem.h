@@ -113,20 +113,24 @@ typedef struct lbmdem_config {
   int32_t map_kernel;       /* particle-link boundary pass: 0 automatic (one
                                block per sphere from 128 spheres when it fits),
                                1 several blocks per sphere (box slabs and row
-                               chunks), 2 one block per sphere (EINVAL if its LDS
-                               cube does not fit), 3 fused: the boundary values
+                               chunks; the mapping from claims of the new
+                               positions), 2 one block per sphere (EINVAL if its
+                               LDS cube does not fit: a periodic axis shorter
+                               than 2 (ceil(max_radius + 3) + 1) + 1 cells; the
+                               mapping updated geometrically where a sphere's
+                               membership changed), 3 fused: the boundary values
                                and momentum exchange are formed inside the sweep
                                and the mapping is updated geometrically; the DEM
                                then runs after the sweep (EINVAL for max_radius
                                below 1); the force sums differ in rounding
                                order                                             */
-  int32_t overlap;          /* 1 (default): inside a step, the one-workgroup DEM
-                               kernels and the claims of the new positions run on
-                               a second, library-owned stream beside the sweep
-                               (they need only the previous step's forces); it
-                               waits on and rejoins the domain's stream within
-                               the step.  0: everything on the domain's stream.
-                               Results are identical.                             */
+  int32_t overlap;          /* 1 (default): inside a step, the DEM kernels and
+                               the claims (or mapping bins) of the new positions
+                               run on a second, library-owned stream beside the
+                               sweep (they need only the previous step's
+                               forces); it waits on and rejoins the domain's
+                               stream within the step.  0: everything on the
+                               domain's stream.  Results are identical.          */
   double body_force[3];     /* fluid body force a (force density, lattice units),
                                Guo's forcing in the collision (test scenarios of
                                Sec. 2.4 such as the Stokes-flow sphere array); it
@@ -326,8 +330,8 @@ const char* lbmdem_batch_last_error(const lbmdem_batch* batch);
 /* Kernel timing with HIP events on the domain's stream (for roofline
  * reports).  enable: 0 off, 1 the sweep only (each event record adds a small
  * gap to the queue, so level 1 disturbs the step least), 2 every kernel group.
- * kernel: 0 fused stream-collide sweep, 1 DEM sub-cycles + mapping claims,
- * 2 reconstruction + mapping commit + boundary values and force partials.
+ * kernel: 0 fused stream-collide sweep, 1 DEM sub-cycles + mapping claims or
+ * bins, 2 reconstruction + mapping update + boundary values and force partials.
  * get returns the summed milliseconds and launch count since enabling. */
 int32_t lbmdem_set_profiling(lbmdem_domain* dom, int32_t enable);
 int32_t lbmdem_get_profile(lbmdem_domain* dom, int32_t kernel, double* total_ms,
