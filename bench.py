@@ -478,7 +478,9 @@ def run_domain(wl, storage_name, args, dev, profile_breakdown=True):
             dom.set_profiling(2)
             dom.step(min(args.steps, 50))
             dom.sync()
-            brk = {k: dom.profile(j) for j, k in enumerate(("sweep", "dem_claims", "recon_commit_bc"))}
+            # kernel groups: the sweep; the DEM with the mapping's claims or bins
+            # (beside the sweep); reconstruction, mapping update and boundary pass
+            brk = {k: dom.profile(j) for j, k in enumerate(("sweep", "dem_map_prepare", "recon_remap_bc"))}
         dom.set_profiling(0)
         ncell = cfg.nx * cfg.ny * cfg.nz
         nfluid = int((dom.field("flags") <= 1).sum())
