@@ -914,6 +914,9 @@ __global__ __launch_bounds__(256) void k_commit(DevDomain d, int in_step, int ad
 // sphere's solid cells that have a non-own neighbour are listed, and their
 // links are formed as in k_commit.  Dynamic LDS: edge^3 state bytes plus the
 // surface list.
+// threads per block of the in-step geometric kernels (one block per sphere)
+constexpr int GEO_THREADS = 64;
+
 // mapping bin of a position
 __device__ __forceinline__ int mbin_index(const DevDomain& d, const double* x, int* b) {
   const int n[3] = {d.nx, d.ny, d.nz};
@@ -1506,12 +1509,12 @@ void launch_update_fused(const DevDomain& d, hipStream_t s) {
   if (d.P > 0) {
     hipLaunchKernelGGL(k_mbins, dim3(gp), dim3(256), 0, s, d, 1, 0);
     if (d.storage == 0)
-      hipLaunchKernelGGL(k_recon_geo<double>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(k_recon_geo<double>, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
     else if (d.storage == 1)
-      hipLaunchKernelGGL(k_recon_geo<float>, dim3((unsigned)d.P), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(k_recon_geo<float>, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
     else
-      hipLaunchKernelGGL(k_recon_geo<__half>, dim3((unsigned)d.P), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(k_recon_geo<__half>, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
+    hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
   }
   hipLaunchKernelGGL(k_advance_fused, dim3(gp), dim3(256), 0, s, d);
 }
@@ -1542,8 +1545,8 @@ static void launch_update_t(const DevDomain& d, bool reconstruct, int in_step, i
     // inside a step: reconstruction and the flags and owners of the new
     // positions (outside, launch_mapping has updated them)
     if (in_step) {
-      if (reconstruct) hipLaunchKernelGGL(k_recon_geo<T>, dim3((unsigned)d.P), dim3(256), 0, s, d);
-      hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(256), 0, s, d);
+      if (reconstruct) hipLaunchKernelGGL(k_recon_geo<T>, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
+      hipLaunchKernelGGL(k_remap_geo, dim3((unsigned)d.P), dim3(GEO_THREADS), 0, s, d);
     }
   } else if (reconstruct) {
     hipLaunchKernelGGL(k_recon<T>, dim3(nsb), dim3(256), 0, s, d, in_step);
