@@ -44,3 +44,17 @@ def test_create_rejects_small_region_without_touching_device():
     rc = L.lib().lbmdem_create(C.byref(c), C.c_void_p(256), 16, None, C.byref(h))
     assert rc == L.ENOMEM and not h.value
     assert b"smaller" in L.lib().lbmdem_last_error(None)
+
+
+def test_ball_pass_domains_hold_cell_words_not_claims():
+    """The slab pass keeps a 64-bit claim word and a 32-bit shell stamp per
+    cell; the one-block-per-sphere pass (geometric mapping update) keeps a
+    32-bit cell word and the mapping bins instead: 8 bytes per cell less,
+    minus the bins (at most 4 x 10^6 bins of 17 ints)."""
+    kw = dict(nx=128, ny=128, nz=128, storage=L.STORE_F32, max_spheres=500, max_radius=6.0)
+    slab = L.footprint_bytes(L.default_config(map_kernel=1, **kw))
+    ball = L.footprint_bytes(L.default_config(map_kernel=2, **kw))
+    N = 128 ** 3
+    bins = 8 * N - (slab - ball)
+    assert slab > 0 and ball > 0
+    assert 0 < bins <= 4 * 17 * (128 // 9) ** 3 + 4 * 256
