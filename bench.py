@@ -536,8 +536,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (how the path "
-                                   "would shard over several GPUs is described in the design notes)"}))
+        print(json.dumps({"error": "the benchmark runs the path on one GPU; --gpus must be 1 (how the "
+                                   "path would shard over several GPUs is described in the design notes)"}))
         raise SystemExit(2)
     if args.workload == "serve":
         serve_bench(args)
