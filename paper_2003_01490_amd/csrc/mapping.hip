@@ -2,9 +2,10 @@
 // fluid boundary conditions (Eq. MEM_CLI) and momentum exchange (Eqs. MEM_Fq,
 // interaction_force, interaction_torque, missing-link compensation).
 //
-// Work is sphere-centric: blocks (sphere i, slab b) walk the cells of the box
-// around the sphere's old and new positions, so the cost scales with the
-// particles, not with the lattice.  Three kernels per mapping update:
+// Work is sphere-centric: blocks walk the cells of the box around a sphere's
+// old and new positions, so the cost scales with the particles, not with the
+// lattice.  Two forms of the mapping update:
+// - slab pass (few spheres; blocks (sphere i, slab b)):
 //   claim    - cells whose centre lies in the closed ball of radius R get an
 //              atomic max-claim (stamp << 32 | ~id): the lowest id wins ties of
 //              overlapping spheres; cells within R + delta_aB get the stamp of
@@ -12,21 +13,28 @@
 //   recon    - cells that were solid of sphere i and are now fluid get
 //              Eq. (PDF_reconstruction) from neighbours that are fluid before
 //              and after (old flags are still in place);
-//   commit   - flags/owner are rewritten from the claims (idempotent), and for
-//              each solid cell y of sphere i and each direction q whose cell
-//              x = y - c_q is fluid, the boundary value f_qbar(x, t+1) of
-//              Eq. (MEM_CLI) is stored in slot qbar of y, where the next sweep
-//              pulls it; its momentum-exchange force (Galilean form, Eq. MEM_Fq)
-//              and torque arm x_b - x_p are summed in FP64 per thread and
-//              reduced per block in a fixed order (no atomics) into
-//              partial[i][b].  Links from y to a wall or to another sphere's
-//              solid are missing links: F_q = 2 w_q c_q with arm y - c_q/2.
-// Inside a step the three kernels run after the sweep and the DEM, before the
-// step control advances the domain: they claim with the next mapping stamp
-// and work on the buffer the sweep has just written (the next current one).
-// A mapping update outside the step (new or moved spheres) works on the
-// current buffer, then takes the new stamp.  (Moving-wall bounce-back is done
-// by the sweep itself.)
+//   commit   - flags/owner are rewritten from the claims (idempotent) and the
+//              links are formed (below);
+// - ball pass (many spheres; one block per sphere) and fused step: the
+//   spheres are filed in mapping bins, and each cell whose membership in a
+//   sphere's ball or shell changed gets the state of the new positions from
+//   the spheres of its 27 bins (k_recon_geo reconstructs, k_remap_geo
+//   rewrites flags, owners and cell words); only the cells near the ends of
+//   the balls' row chords are tested.  The ball pass then forms the links
+//   from the cell words.
+// Links: for each solid cell y of sphere i and each direction q whose cell
+// x = y - c_q is fluid, the boundary value f_qbar(x, t+1) of Eq. (MEM_CLI) is
+// stored in slot qbar of y, where the next sweep pulls it; its
+// momentum-exchange force (Galilean form, Eq. MEM_Fq) and torque arm
+// x_b - x_p are summed in FP64 per thread and reduced per block in a fixed
+// order (no atomics) into partial[i][b].  Links from y to a wall or to another
+// sphere's solid are missing links: F_q = 2 w_q c_q with arm y - c_q/2.
+// Inside a step these kernels run after the sweep and the DEM (the claims or
+// bins beside the sweep), before the step control advances the domain: they
+// use the next mapping stamp and work on the buffer the sweep has just
+// written (the next current one).  A mapping update outside the step (new or
+// moved spheres) works on the current buffer, then takes the new stamp.
+// (Moving-wall bounce-back is done by the sweep itself.)
 // The squared distances are formed as (dx*dx + dy*dy) + dz*dz in FP64 without
 // contraction, so that the flags are a deterministic function of the FP64
 // positions.
