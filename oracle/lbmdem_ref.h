@@ -82,14 +82,15 @@ void ref_lubrication(const ref_config* cfg, const double* xi, const double* ui,
                      const double* uj, const double* wj, double Rj, int32_t wall,
                      double* F, double* T);
 
-/* collision time for a contact of (mean) diameter D: config value or
- * Eq. (collisionTimeChoice); minimal lubrication gap for radius R: config
- * value or Eq. (lubricationGapSize) */
 /* Eq. (MEM_CLI): boundary value of one particle link (direction q from the
  * fluid cell x to the solid cell x + c_q; r = x - x_p; Aq = f~_q(x),
  * Aqb = f~_qbar(x), Aqm = f~_q(x - c_q) used when cli != 0); NaN for a bad q */
 double ref_link_value(int32_t q, const double* r, double R, const double* u, const double* w, double Aq,
                       double Aqb, double Aqm, int32_t cli);
+
+/* collision time for a contact of (mean) diameter D: config value or
+ * Eq. (collisionTimeChoice); minimal lubrication gap for radius R: config
+ * value or Eq. (lubricationGapSize) */
 double ref_collision_time(const ref_config* cfg, double D);
 double ref_min_gap(const ref_config* cfg, double R);
 
